@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Throughput of the differentiable Gaussian rasterizer on one MI355X.
+
+Workload (default): 3M-Gaussian SH-3 city block, 16 views of uneven size
+(6 x 1920x1080, 6 x 1600x900, 4 x 960x540), one fused forward + L1 + backward
+step of all views per step, captured in one HIP graph (batched form).  The
+same step is also timed as 16 plain per-view launch chains.  Inputs are
+seeded synthetic data already resident in device memory.
+
+Prints one JSON line: Mpixels/s of the batched step (value), Gaussians/s,
+the plain per-view rate and the ratio, the roofline of the dominant kernel
+(timed with device events on its stream over a second pass of eager steps),
+a sampled parity check of the timed outputs against the FP64 oracle, and the
+oracle's own rate on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+# Algorithmic float operations per evaluated (pixel, Gaussian) pair, counted
+# from the method (not from the instructions): forward offset (2), quadratic
+# form (6), exponent and opacity (2), threshold tests (2), transmittance
+# update (2), colour accumulation (7) = 21; reverse pass: the same alpha (12),
+# transmittance recovery (2), dL/dalpha over 3 channels (12), colour and
+# suffix updates (9), opacity/mean/conic partials (14), 9-way reduction
+# share (9) = 58.
+FLOPS_FWD_PAIR = 21
+FLOPS_BWD_PAIR = 58
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--tile", default=None, help="fixed tile shape WxH when not autotuning")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (blocks train independently, one "
+              "GPU each); run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2510_01767_amd import gsr as C
+    from paper_2510_01767_amd import scenes
+    from paper_2510_01767_amd.raster import Rasterizer, camera_tensor, pack_images, scene_tensors
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    C.load(build_if_missing=False)
+    t0 = time.time()
+    scene = scenes.make_config(args.config)
+    log(f"scene {scene.name}: {scene.n} Gaussians, {scene.n_views} views, {scene.pixels} pixels "
+        f"({time.time() - t0:.1f} s)")
+    sizes = [(c["W"], c["H"]) for c in scene.cameras]
+    params = scene_tensors(scene)
+    cams = camera_tensor(scene.cameras)
+    targets = torch.from_numpy(pack_images(scene.targets)).cuda()
+    torch.cuda.synchronize()
+
+    tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else (16, 16)
+    rb = Rasterizer(scene.n, scene.sh_degree, sizes, mode="batched", tile=tile, profile_stages=1)
+    rb.step_l1(params, cams, targets, stats=False)
+    counts = rb.counts()
+    log(f"visible {counts.visible_total}, union {counts.visible_union}, intersections "
+        f"{counts.intersections_total}, capacity {rb.layout.capacity}")
+    if not args.no_autotune:
+        best, ms = rb.autotune(params, cams, targets, reps=2)
+        log(f"autotune: tile {best.tile_w}x{best.tile_h}, lds_batch {best.lds_batch}, grid/CU "
+            f"{best.grid_per_cu}, bwd {best.bwd_variant}: {ms:.3f} ms")
+    opt = rb.options
+
+    # ---- timed region: K replays of the captured batched step
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        rb.capture(params, cams, targets, stats=False)
+    stream.synchronize()
+    for _ in range(args.warmup):
+        rb.launch(stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        rb.launch(stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_batched = e0.elapsed_time(e1) / args.steps
+    log(f"batched graph step {ms_batched:.3f} ms (wall {1000 * wall / args.steps:.3f} ms)")
+    counts = rb.counts()
+    images_gpu = rb.images.cpu().numpy()
+    loss_gpu = float(rb.loss.item())
+    last = rb.ws_tensor("pix_last", torch.int32, rb.pixels).cpu().numpy().astype(np.int64)
+    pairs = int(last.sum())
+
+    # ---- per-kernel device time: the same step eagerly, stage events on its stream
+    stage_tot = {}
+    with torch.cuda.stream(stream):
+        for _ in range(args.steps):
+            rb.step_l1(params, cams, targets, stats=False, stream=stream)
+            for name, (ms, k) in C.gsr_last_stage_times(rb.plan).items():
+                a = stage_tot.setdefault(name, [0.0, 0])
+                a[0] += ms
+                a[1] += k
+    torch.cuda.synchronize()
+    stage_ms = {k: v[0] / args.steps for k, v in stage_tot.items()}
+    log("stages (ms/step): " + ", ".join(f"{k} {v:.3f}" for k, v in sorted(stage_ms.items(), key=lambda x: -x[1])))
+    dom = max(stage_ms, key=stage_ms.get)
+
+    # ---- plain per-view launches
+    ms_plain = None
+    if not args.no_plain:
+        rp = Rasterizer(scene.n, scene.sh_degree, sizes, mode="plain", tile=(16, 16))
+        rp.step_l1(params, cams, targets, stats=False)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            rp.step_l1(params, cams, targets, stats=False)
+        torch.cuda.synchronize()
+        ms_plain = 1000 * (time.perf_counter() - w0) / args.plain_steps
+        log(f"plain per-view step {ms_plain:.3f} ms")
+        del rp
+
+    # ---- algorithmic work of the dominant kernel
+    n, V = scene.n, scene.n_views
+    P = scene.pixels
+    I = counts.intersections_total
+    vis = counts.visible_total
+    K = 3 * (scene.sh_degree + 1) ** 2
+    roof = None
+    if dom == "fused raster":
+        flops = pairs * (FLOPS_FWD_PAIR + FLOPS_BWD_PAIR)
+        achieved = flops / (stage_ms[dom] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None, "kernel": "k_fused",
+                "pairs": pairs, "flops_per_pair": FLOPS_FWD_PAIR + FLOPS_BWD_PAIR}
+    else:
+        # per-Gaussian streams (project / project_bwd / emit / sort) are bound by HBM
+        bytes_by_stage = {
+            "project": 44 * n + (4 * K + 64 + 48) * vis,
+            "project_bwd": 4 * n + (4 * (11 + K)) * n * 2 + 48 * vis,
+            "emit": 4 * n + 20 * vis + 8 * I,
+            "sort": 16 * I,
+        }
+        b = bytes_by_stage.get(dom, 0)
+        achieved = b / (stage_ms[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom}
+    roof["stage_ms"] = {k: round(v, 4) for k, v in stage_ms.items()}
+
+    # ---- sampled parity of the timed outputs + the oracle's own rate
+    parity = None
+    cpu = None
+    if not (args.no_parity and args.no_cpu):
+        import oracle
+        v = int(np.argmin([w * h for w, h in sizes]))
+        c = scene.cameras[v]
+        W, H = c["W"], c["H"]
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        Pn = oracle.Params.from_scene(scene)
+        o = oracle.default_opts(tile_w=opt.tile_w, tile_h=opt.tile_h)
+        t1 = time.time()
+        fo = oracle.forward(Pn, [c], o)
+        img_o = fo["images"][0]
+        d = np.sign(img_o - scene.targets[v]) / (3.0 * W * H * V)
+        bo = oracle.backward(Pn, [c], o, fo, [d])
+        t_ora = time.time() - t1
+        off = 3 * sum(w * h for w, h in sizes[:v])
+        img_g = images_gpu[off:off + 3 * W * H].reshape(3, H, W).astype(np.float64)
+        amb = fo["ambiguous"][0].astype(bool)
+        err = np.abs(img_g - img_o) / np.maximum(1.0, np.abs(img_o))
+        rel_l2 = float(np.linalg.norm(img_g - img_o) / np.linalg.norm(img_o))
+        g2d = rb.ws_tensor("grad2d", torch.float32, 12 * rb.layout.vn).view(-1, 12)[v * n:(v + 1) * n, :9]
+        g2d = g2d.cpu().numpy().astype(np.float64)
+        go = bo["g2d"].T
+        visv = fo["records"][0]["visible"].astype(bool)
+        g_rel = float(np.linalg.norm(g2d[visv] - go[visv]) / np.linalg.norm(go[visv]))
+        parity = {"view": v, "size": [W, H], "image_max_rel": float(err[:, ~amb].max()),
+                  "image_rel_l2": rel_l2, "ambiguous_pixels": int(amb.sum()),
+                  "grad2d_rel_l2": g_rel,
+                  "pass": bool(err[:, ~amb].max() <= 1e-5 and rel_l2 <= 1e-5 and g_rel <= 1e-3)}
+        log(f"parity view {v}: {parity}")
+        cpu = {"value": round(W * H / t_ora / 1e6, 5), "unit": "Mpixels/s", "cores": threads, "kind": "oracle",
+               "sample": f"FP64 oracle forward + L1 + backward of view {v} ({W}x{H}) of the same workload, "
+                         f"{t_ora:.1f} s"}
+
+    mpix = P / (ms_batched * 1e-3) / 1e6
+    out = {
+        "metric": "fwd+bwd Mpixels/s and Gaussians/s (batched vs per-view) at 1e-5 image tol",
+        "value": round(mpix, 2),
+        "unit": "Mpixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_batched, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": scene.name, "gaussians": n, "views": V, "pixels": P,
+                   "form": "batched fused fwd+L1+bwd, one HIP graph",
+                   "tile": f"{opt.tile_w}x{opt.tile_h}", "lds_batch": opt.lds_batch,
+                   "grid_per_cu": opt.grid_per_cu, "bwd_variant": "stored" if counts.bwd_variant == 2 else "recompute"},
+        "gaussians_per_s": round(n * V / (ms_batched * 1e-3), 1),
+        "visible_gaussian_views_per_s": round(vis / (ms_batched * 1e-3), 1),
+        "plain_ms_per_step": None if ms_plain is None else round(ms_plain, 3),
+        "plain_mpixels_per_s": None if ms_plain is None else round(P / (ms_plain * 1e-3) / 1e6, 2),
+        "batched_vs_plain": None if ms_plain is None else round(ms_plain / ms_batched, 3),
+        "loss": loss_gpu,
+        "counts": {"visible": vis, "union": counts.visible_union, "intersections": I, "pairs": pairs},
+        "roofline": roof,
+        "parity": parity,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

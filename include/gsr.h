@@ -1,0 +1,264 @@
+/*
+ * gsr.h - C ABI of the MI355X differentiable Gaussian rasterizer.
+ *
+ * The operation.  One fine-training step of a LoBE-GS block (arXiv
+ * 2510.01767) renders every camera assigned to the block from the block's
+ * Gaussians and back-propagates an image loss to the Gaussian parameters
+ * (Sec. 3, Fig. 1 "parallel fine-tuning"; the per-block training follows
+ * vanilla 3DGS, App. A.1).  The library computes, for n Gaussians and
+ * n_views cameras:
+ *   - per-view visibility (frustum culling during rasterization, Sec. 3.3)
+ *     and the visibility-cropping mask over a block's cameras (Sec. 3.3, VC);
+ *   - EWA projection with scale/quaternion covariance and SH colour;
+ *   - tile binning and per-tile ordering by (depth, Gaussian index);
+ *   - front-to-back alpha compositing (Sec. 3.2, blending equation);
+ *   - the L1 image loss, the hand-written reverse pass to every parameter,
+ *     and the per-Gaussian view-space gradient statistic plus visible count
+ *     that selective densification reads (Sec. 3.3, SD).
+ *
+ * Conventions (all fields of gsr_options, defaults from gsr_default_options):
+ *   pinhole camera, OpenCV axes (x right, y down, z forward), world->camera
+ *   [R | t]; pixel centres at (px + 1/2, py + 1/2); near 0.01, far 1e10;
+ *   2D covariance J W Sigma W^T J^T + 0.3 I with x/z, y/z clamped to 1.3
+ *   half fields of view inside J; radius ceil(3 sqrt(lambda_max)); tile
+ *   rectangle floor((mean +- r) / tile) clamped to the grid; alpha =
+ *   min(0.99, o exp(p)), entries below 1/255 skipped, compositing stops
+ *   before an entry that would drop T below 1e-4; background bg (black);
+ *   colour = max(0, sum_k sh_k Y_k(dir) + 1/2) with the real orthonormal SH
+ *   basis (Condon-Shortley phase, l-major, m = -l..l), dir from the camera
+ *   centre to the mean; opacity = sigmoid(logit); scale = exp(log_scale);
+ *   rotation = unit quaternion q / |q| in (w, x, y, z) order.
+ *
+ * Memory.  The caller owns every device buffer (parameters, gradients,
+ * statistics, images, targets, cameras, workspace).  The library never
+ * allocates device memory; it enqueues work on the caller's stream.  A plan
+ * holds only host metadata and, after gsr_graph_capture, a graph.
+ *
+ * Errors.  Every call returns a gsr_status; nothing is printed and no call
+ * aborts.  Argument errors are detected on the host before anything is
+ * enqueued.  GSR_ERR_CAPACITY comes from a sticky device flag (the
+ * intersection capacity was exceeded; outputs are invalid - grow
+ * capacity_intersections and retry) and is reported by gsr_query_counts, or
+ * directly by plain-mode calls, which read the per-view counts back.
+ * GSR_ERR_HIP carries the runtime's message in gsr_last_error.  A plan is not
+ * thread-safe; distinct plans are independent.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gsr_status;
+#define GSR_OK 0
+#define GSR_ERR_INVALID_ARG 1
+#define GSR_ERR_WORKSPACE_TOO_SMALL 2
+#define GSR_ERR_CAPACITY 3
+#define GSR_ERR_NONFINITE 4
+#define GSR_ERR_HIP 5
+#define GSR_ERR_STATE 6 /* call order: backward before forward, launch before capture */
+
+#define GSR_MAX_VIEWS 32
+#define GSR_MAX_IMAGE_SIDE 16384
+
+/* Execution form. */
+#define GSR_MODE_PLAIN 0   /* one launch chain per view, per-view count read-back */
+#define GSR_MODE_BATCHED 1 /* all views in one chain, persistent fused raster, capturable */
+
+/* Reverse-compositing form (Sec. "(3) differentiation"). */
+#define GSR_BWD_AUTO 0      /* stored history if it fits history_budget_bytes, else recompute */
+#define GSR_BWD_RECOMPUTE 1 /* recover T_i = T_{i+1} / (1 - alpha_i) walking back */
+#define GSR_BWD_STORED 2    /* read the per-(entry, pixel) transmittance saved by the forward */
+
+/* One camera; the array lives in device memory so graph replays may take new
+ * poses.  64 bytes. */
+typedef struct gsr_camera {
+  float R[9]; /* world -> camera rotation, row major */
+  float t[3]; /* world -> camera translation */
+  float fx, fy, cx, cy;
+} gsr_camera;
+
+typedef struct gsr_options {
+  int32_t mode;          /* GSR_MODE_* */
+  int32_t tile_w;        /* 16x16, 32x8 or 8x32 (width x height), 256 pixels */
+  int32_t tile_h;
+  int32_t bwd_variant;   /* GSR_BWD_* */
+  int32_t lds_batch;     /* list entries staged in LDS per round: 64, 128 or 256 */
+  int32_t grid_per_cu;   /* persistent raster grid = grid_per_cu * compute units (1..32) */
+  int32_t accumulate_grads; /* 0: gradients are overwritten; 1: added to */
+  int32_t check_finite;  /* 1: flag non-finite parameters (GSR_ERR_NONFINITE via query) */
+  int32_t profile_stages; /* 1: time every stage of eager calls with device events */
+  int32_t reserved;
+  float near_plane, far_plane;
+  float eps2d;           /* low-pass dilation of the 2D covariance */
+  float sigma_extent;    /* footprint radius in standard deviations */
+  float jac_clamp;       /* x/z, y/z clamp inside J, in half fields of view */
+  float alpha_min, alpha_max, T_min;
+  float bg[3];
+  float stat_scale;      /* densification statistic scale; <= 0 means n_views */
+  int64_t capacity_intersections; /* static capacity of (tile, Gaussian) entries;
+                                     0: 4 n n_views (at least 65536, at most 2^31) */
+  int64_t history_budget_bytes;   /* device bytes the stored history may use (AUTO/STORED) */
+} gsr_options;
+
+/* Static shape of a problem; widths/heights are host arrays [n_views]. */
+typedef struct gsr_problem {
+  int64_t n;
+  int32_t sh_degree; /* 0..3; K = (sh_degree + 1)^2 coefficients per channel */
+  int32_t n_views;   /* 1..GSR_MAX_VIEWS */
+  const int32_t *widths;
+  const int32_t *heights;
+} gsr_problem;
+
+/* Device pointers to structure-of-arrays float32 planes of length n. */
+typedef struct gsr_gaussians {
+  const float *means;          /* [3][n] */
+  const float *log_scales;     /* [3][n] */
+  const float *quats;          /* [4][n], (w, x, y, z), need not be unit */
+  const float *opacity_logits; /* [n] */
+  const float *sh;             /* [3K][n], plane k*3 + channel */
+  const uint8_t *keep;         /* [n] or NULL: Gaussians with keep = 0 are culled */
+} gsr_gaussians;
+
+/* Gradient planes, same layout as gsr_gaussians (device). */
+typedef struct gsr_grads {
+  float *means, *log_scales, *quats, *opacity_logits, *sh;
+} gsr_grads;
+
+/* Densification statistics (device, accumulated across calls; the caller
+ * resets them).  Either pointer may be NULL to skip it. */
+typedef struct gsr_stats {
+  float *grad2d_norm_sum;  /* [n] += stat_scale * |dL/dmean2d|_2 per visible view */
+  uint32_t *visible_count; /* [n] += 1 per view in which the Gaussian is visible */
+} gsr_stats;
+
+typedef struct gsr_counts {
+  int64_t visible[GSR_MAX_VIEWS];       /* visible Gaussians per view */
+  int64_t intersections[GSR_MAX_VIEWS]; /* (tile, Gaussian) entries per view */
+  int64_t visible_total, intersections_total;
+  int64_t visible_union; /* Gaussians visible in at least one view */
+  int32_t overflow;      /* 1 when capacity_intersections was exceeded */
+  int32_t nonfinite;     /* 1 when check_finite found a non-finite parameter */
+  int32_t tile_w, tile_h, bwd_variant, lds_batch, grid_per_cu, mode;
+} gsr_counts;
+
+/* Internal byte offsets of the workspace (for tests and profiling). */
+typedef struct gsr_layout {
+  size_t header, view_table, view_bits, records, grad2d, tile_count, tile_start, tile_fill,
+      tile_loss, tile_order, keys, keys_alt, pix_T, pix_last, pix_dLdC, history, total;
+  int64_t vn;              /* n_views * n record slots (record of (v, i) at v * n + i) */
+  int64_t tiles_total;     /* tiles over all views for the plan's tile shape */
+  int64_t pixels_total;
+  int64_t capacity;        /* intersection capacity */
+  int64_t history_entries; /* stored-history capacity in (entry, pixel) pairs, 0 if none */
+} gsr_layout;
+
+typedef struct gsr_plan gsr_plan;
+
+/* Fills *opt with the defaults above (plain mode, 16x16 tiles, recompute backward,
+ * LDS batch 128, 4 persistent workgroups per compute unit). */
+void gsr_default_options(gsr_options *opt);
+
+/* Creates a plan for a static problem shape.  Host only (no device call).
+ * INVALID_ARG: null pointers, n <= 0, n * n_views >= 2^32, sh_degree outside
+ * 0..3, n_views outside 1..32, a side outside 1..16384, an unsupported tile
+ * shape, lds_batch or grid_per_cu out of range, non-positive thresholds. */
+gsr_status gsr_plan_create(gsr_plan **plan, const gsr_problem *problem, const gsr_options *opt);
+gsr_status gsr_plan_destroy(gsr_plan *plan);
+
+/* Workspace bytes for this plan: large enough for every tile shape, so the
+ * autotuner may switch shapes within one workspace.  Host only. */
+gsr_status gsr_workspace_size(const gsr_plan *plan, size_t *bytes);
+gsr_status gsr_workspace_layout(const gsr_plan *plan, gsr_layout *layout);
+
+/* Pixel offset of view v inside the packed image/target buffers
+ * (images are [3][H_v][W_v] per view, back to back; offset in floats). */
+gsr_status gsr_image_offset(const gsr_plan *plan, int32_t view, int64_t *offset_floats);
+
+/* Forward render of every view (Sec. 3.2 blending; frustum culling Sec. 3.3).
+ * images: packed [3][H][W] per view (device, written).  Keeps what the
+ * reverse pass needs in the workspace.  T_final/last may be NULL. */
+gsr_status gsr_forward(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams,
+                       float *images, float *T_final, uint32_t *last, void *ws, size_t ws_bytes,
+                       void *stream);
+
+/* Reverse pass for an arbitrary image gradient dL_dimages (packed like
+ * images) after gsr_forward on the same plan and workspace.  Writes grads
+ * (or adds, with accumulate_grads) and accumulates stats (may be NULL). */
+gsr_status gsr_backward(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams,
+                        const float *dL_dimages, const gsr_grads *grads, const gsr_stats *stats,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* One fused training step: forward, L = mean over views of the per-view mean
+ * |image - target|, reverse pass (dL/dimage = sign(image - target) /
+ * (3 H W n_views), sign(0) = 0), statistics.  loss: one device float. */
+gsr_status gsr_forward_backward_l1(gsr_plan *plan, const gsr_gaussians *g,
+                                   const gsr_camera *cams, const float *targets, float *images,
+                                   float *loss, const gsr_grads *grads, const gsr_stats *stats,
+                                   void *ws, size_t ws_bytes, void *stream);
+
+/* Visibility cropping over the plan's views (Sec. 3.3): view_bits[i] has bit
+ * v set when Gaussian i is visible in view v; keep_out[i] = (view_bits != 0);
+ * in_block[i] = 1 when the mean lies in the half-open box aabb = (xmin, ymin,
+ * zmin, xmax, ymax, zmax) (host array).  Any output pointer may be NULL. */
+gsr_status gsr_visibility_mask(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams,
+                               const float *aabb, uint32_t *view_bits, uint8_t *keep_out,
+                               uint8_t *in_block, void *ws, size_t ws_bytes, void *stream);
+
+/* Records the batched fused step (same arguments as gsr_forward_backward_l1)
+ * into a graph owned by the plan; gsr_graph_launch replays it on a stream.
+ * The stream must be capturable (not the legacy null stream).  Requires
+ * GSR_MODE_BATCHED.  Replays read the same buffers, so new parameters or
+ * poses are taken by writing into them. */
+gsr_status gsr_graph_capture(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams,
+                             const float *targets, float *images, float *loss,
+                             const gsr_grads *grads, const gsr_stats *stats, void *ws,
+                             size_t ws_bytes, void *stream);
+gsr_status gsr_graph_launch(gsr_plan *plan, void *stream);
+
+/* Synchronises the stream and reads the counts of the last step from the
+ * workspace.  Returns GSR_ERR_CAPACITY / GSR_ERR_NONFINITE when the
+ * corresponding flag is set (counts are still filled in). */
+gsr_status gsr_query_counts(gsr_plan *plan, const void *ws, gsr_counts *counts, void *stream);
+
+/* Times the batched fused step for each candidate (tile shape 16x16, 32x8,
+ * 8x32; lds_batch; grid_per_cu; backward variant within the history budget)
+ * with device events and stores the fastest in the plan.  *best receives the
+ * choice (fields tile_w/tile_h/bwd_variant/lds_batch/grid_per_cu); best_ms
+ * the time of one step (may be NULL). */
+gsr_status gsr_autotune(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams,
+                        const float *targets, float *images, float *loss, const gsr_grads *grads,
+                        void *ws, size_t ws_bytes, int32_t reps, gsr_options *best,
+                        float *best_ms, void *stream);
+
+/* Per-stage device time of the last eager call made with profile_stages = 1
+ * (graph replays are not timed).  Synchronises on the recorded events.
+ * Stages with the same name (one per view in the plain form) are summed;
+ * launches counts them. */
+#define GSR_MAX_STAGES 16
+typedef struct gsr_stage_times {
+  int32_t count;
+  int32_t launches[GSR_MAX_STAGES];
+  float ms[GSR_MAX_STAGES];
+  char name[GSR_MAX_STAGES][32];
+} gsr_stage_times;
+gsr_status gsr_last_stage_times(gsr_plan *plan, gsr_stage_times *out);
+
+/* Current options of a plan (after autotuning). */
+gsr_status gsr_plan_options(const gsr_plan *plan, gsr_options *opt);
+/* Changes the tuning fields (tile_w, tile_h, bwd_variant, lds_batch,
+ * grid_per_cu) of a plan; drops a captured graph. */
+gsr_status gsr_plan_set_tuning(gsr_plan *plan, const gsr_options *opt);
+
+const char *gsr_status_string(gsr_status s);
+const char *gsr_last_error(const gsr_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSR_H */

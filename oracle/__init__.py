@@ -114,7 +114,8 @@ def _declare(L):
     L.ora_bin.argtypes = [ctypes.c_int64, _i32, _i32, _u32, _i64, _i64, _i32, ctypes.c_int64,
                           ctypes.c_int64, _i64, _u32, _i64, _i64]
     L.ora_render.argtypes = [_O, ctypes.c_int32, ctypes.c_int32, _i64, _i64, ctypes.c_int64,
-                             _d, _d, _d, _d, _d, _u8, ctypes.c_double, _d, _d, _i32, _d, _u8, _i64]
+                             _d, _d, _d, _d, _d, _u8, ctypes.c_double, ctypes.c_double, _d, _d, _i32, _d,
+                             _u8, _i64]
     L.ora_render_brute.argtypes = [_O, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _i32, _i32,
                                    _u32, _i64, _d, _d, _d, _d, _d, _d, _d, _i32]
     L.ora_render_bwd.argtypes = [_O, ctypes.c_int32, ctypes.c_int32, _i64, _i64, ctypes.c_int64,
@@ -234,8 +235,17 @@ def _records_view(recs):
                                 "rect", "margin", "grad_margin")}
 
 
-def forward(P: Params, cams: list, opts: Opts, keep=None, delta=1e-5) -> dict:
-    """Full multi-view forward: records, binning, per-pixel compositing."""
+DELTA_GAUSS = 1e-9   # per-Gaussian decisions: both sides evaluate them in float64
+DELTA_ALPHA = 4e-6   # alpha thresholds: a float32 alpha carries <= ~1.5e-6 relative error
+DELTA_T = 2e-5       # stop decision: float32 transmittance after ~1000 factors
+
+
+def forward(P: Params, cams: list, opts: Opts, keep=None, delta=DELTA_GAUSS, delta_alpha=DELTA_ALPHA,
+            delta_T=DELTA_T) -> dict:
+    """Full multi-view forward: records, binning, per-pixel compositing.
+
+    delta* are the relative margins below which a discrete decision is called
+    ambiguous (another correct implementation may take it the other way)."""
     n = P.n
     V = len(cams)
     recs = [project(P, c, opts, keep) for c in cams]
@@ -264,20 +274,31 @@ def forward(P: Params, cams: list, opts: Opts, keep=None, delta=1e-5) -> dict:
         rv = np.ascontiguousarray(bins["ranges"][tile_base_v[v]:tile_base_v[v] + tiles_per_view[v]])
         L.ora_render(ctypes.byref(opts), W, H, _p(rv, _i64), _p(bins["values"], _i64), nr,
                      _p(R["mean2d"], _d), _p(R["conic"], _d), _p(R["opacity"], _d),
-                     _p(R["color"], _d), _p(R["depth"], _d), _p(rec_amb, _u8), delta,
+                     _p(R["color"], _d), _p(R["depth"], _d), _p(rec_amb, _u8), delta_alpha, delta_T,
                      _p(img, _d), _p(t, _d), _p(la, _i32), _p(d, _d), _p(a, _u8), _p(sg, _i64))
-        # Gaussians whose own decisions are ambiguous may cover one more tile
-        # row or column on another implementation: mark that whole area.
+        # A Gaussian whose own decisions are ambiguous may be listed in one
+        # more tile row or column by another implementation: mark the pixels
+        # of that enlarged area where it could contribute (alpha above half
+        # the skip threshold), or the whole area when it has no 2D shape.
         idx = np.nonzero(recs[v]["margin"] < delta)[0]
         tw, th = opts.tile_w, opts.tile_h
         gx, gy = grids[v]
+        rv = recs[v]
         for i in idx:
-            if recs[v]["radius"][i] == 0 and not recs[v]["visible"][i]:
+            if rv["radius"][i] == 0 and not rv["visible"][i]:
                 continue
-            x0, y0, x1, y1 = recs[v]["rect"][:, i]
+            x0, y0, x1, y1 = rv["rect"][:, i]
             x0, y0 = max(min(x0, gx - 1) - 1, 0), max(min(y0, gy - 1) - 1, 0)
             x1, y1 = min(max(x1, 0) + 1, gx - 1), min(max(y1, 0) + 1, gy - 1)
-            a[y0 * th:(y1 + 1) * th, x0 * tw:(x1 + 1) * tw] = 1
+            ys, xs = np.mgrid[y0 * th:min((y1 + 1) * th, H), x0 * tw:min((x1 + 1) * tw, W)]
+            A, B, Cc = rv["conic"][:, i]
+            if A > 0 and Cc > 0:
+                dx = xs + 0.5 - rv["mean2d"][0, i]
+                dy = ys + 0.5 - rv["mean2d"][1, i]
+                al = rv["opacity"][i] * np.exp(-0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy)
+                a[ys[al >= 0.5 * opts.alpha_min], xs[al >= 0.5 * opts.alpha_min]] = 1
+            else:
+                a[ys, xs] = 1
         images.append(img)
         sigs.append(sg)
         Tf.append(t)
@@ -344,7 +365,7 @@ def split_grads(grads: np.ndarray) -> dict:
                 sh_dc=grads[11:14], sh_rest=grads[14:])
 
 
-def step_l1(P: Params, cams: list, targets: list, opts: Opts, keep=None, delta=1e-5) -> dict:
+def step_l1(P: Params, cams: list, targets: list, opts: Opts, keep=None, delta=DELTA_GAUSS) -> dict:
     """One fine-training step of the rasterizer: forward, L1, backward."""
     fwd = forward(P, cams, opts, keep, delta)
     loss, dimg = l1_loss(fwd["images"], targets)

@@ -360,9 +360,9 @@ int64_t ora_bin(int64_t n_rec, const int32_t *rect /* [4][n_rec] */, const int32
  * Output colour C + T bg, final T, and `last` = number of list entries
  * processed before the stop (or the list length).
  * Records are planes indexed by record id: mean2d [2][nr], conic [3][nr],
- * opacity [nr], color [3][nr], depth [nr].  amb_* fields mark a pixel as
- * ambiguous when any pair decision has relative margin below delta or when a
- * record flagged ambiguous appears in its list.
+ * opacity [nr], color [3][nr], depth [nr].  A pixel is marked ambiguous when
+ * an alpha decision has relative margin below delta, the stop decision one
+ * below delta_T, or a record flagged ambiguous could blend into it.
  */
 typedef struct {
   int64_t nr;
@@ -371,7 +371,7 @@ typedef struct {
 } ora_records;
 
 static int composite_pixel(const ora_opts *o, const ora_records *rc, const int64_t *vals,
-                           int64_t len, double px, double py, double delta, double C[3], double *D,
+                           int64_t len, double px, double py, double delta, double delta_T, double C[3], double *D,
                            double *Tout, int *amb, double *alpha_hist, double *T_hist,
                            int64_t *sig) {
   double T = 1.0;
@@ -382,7 +382,6 @@ static int composite_pixel(const ora_opts *o, const ora_records *rc, const int64
   int64_t j;
   for (j = 0; j < len; j++) {
     int64_t r = vals[j];
-    if (rc->rec_amb && rc->rec_amb[r]) *amb = 1;
     double dx = px + 0.5 - rc->mean2d[r];
     double dy = py + 0.5 - rc->mean2d[rc->nr + r];
     double A = rc->conic[r], B = rc->conic[rc->nr + r], Cc = rc->conic[2 * rc->nr + r];
@@ -390,11 +389,13 @@ static int composite_pixel(const ora_opts *o, const ora_records *rc, const int64
     if (alpha_hist) alpha_hist[j] = 0;
     if (p > 0) continue;
     double raw = rc->opacity[r] * exp(p);
+    /* a record with an ambiguous decision of its own matters where it could blend */
+    if (rc->rec_amb && rc->rec_amb[r] && raw >= 0.5 * o->alpha_min) *amb = 1;
     if (rel_margin(raw, o->alpha_min) < delta || rel_margin(raw, o->alpha_max) < delta) *amb = 1;
     double alpha = raw < o->alpha_max ? raw : o->alpha_max;
     if (alpha < o->alpha_min) continue;
     double Tn = T * (1.0 - alpha);
-    if (rel_margin(Tn, o->T_min) < delta) *amb = 1;
+    if (rel_margin(Tn, o->T_min) < delta_T) *amb = 1;
     if (Tn < o->T_min) break;
     for (int ch = 0; ch < 3; ch++) C[ch] += alpha * T * rc->color[ch * rc->nr + r];
     *D += alpha * T * rc->depth[r];
@@ -412,7 +413,7 @@ static int composite_pixel(const ora_opts *o, const ora_records *rc, const int64
 void ora_render(const ora_opts *o, int32_t W, int32_t H, const int64_t *ranges_view,
                 const int64_t *values, int64_t nr, const double *mean2d, const double *conic,
                 const double *opacity, const double *color, const double *depth,
-                const uint8_t *rec_amb, double delta, double *image, double *T_final,
+                const uint8_t *rec_amb, double delta, double delta_T, double *image, double *T_final,
                 int32_t *last, double *depth_out, uint8_t *ambiguous, int64_t *signature) {
   ora_records rc = {nr, mean2d, conic, opacity, color, depth, rec_amb};
   int tiles_x = (W + o->tile_w - 1) / o->tile_w;
@@ -425,7 +426,7 @@ void ora_render(const ora_opts *o, int32_t W, int32_t H, const int64_t *ranges_v
     double C[3], D, T;
     int amb;
     int64_t sg;
-    int n = composite_pixel(o, &rc, values + s, e - s, px, py, delta, C, &D, &T, &amb, NULL, NULL, &sg);
+    int n = composite_pixel(o, &rc, values + s, e - s, px, py, delta, delta_T, C, &D, &T, &amb, NULL, NULL, &sg);
     for (int ch = 0; ch < 3; ch++) image[ch * P + pix] = C[ch] + T * o->bg[ch];
     T_final[pix] = T;
     last[pix] = n;
@@ -472,7 +473,7 @@ void ora_render_brute(const ora_opts *o, int32_t W, int32_t H, int64_t nr, const
     for (int64_t k = 0; k < m; k++) vals[k] = list[k].rec;
     double C[3], D, T;
     int amb;
-    int n = composite_pixel(o, &rc, vals, m, px, py, 0.0, C, &D, &T, &amb, NULL, NULL, NULL);
+    int n = composite_pixel(o, &rc, vals, m, px, py, 0.0, 0.0, C, &D, &T, &amb, NULL, NULL, NULL);
     for (int ch = 0; ch < 3; ch++) image[ch * P + pix] = C[ch] + T * o->bg[ch];
     T_final[pix] = T;
     last[pix] = n;
@@ -509,7 +510,7 @@ void ora_render_bwd(const ora_opts *o, int32_t W, int32_t H, const int64_t *rang
     double *ah = malloc(sizeof(double) * len), *th = malloc(sizeof(double) * len);
     double C[3], D, T;
     int amb;
-    int n = composite_pixel(o, &rc, values + s, len, px, py, 0.0, C, &D, &T, &amb, ah, th, NULL);
+    int n = composite_pixel(o, &rc, values + s, len, px, py, 0.0, 0.0, C, &D, &T, &amb, ah, th, NULL);
     double g[3] = {dL_dimg[pix], dL_dimg[P + pix], dL_dimg[2 * P + pix]};
     double Bacc[3] = {T * o->bg[0], T * o->bg[1], T * o->bg[2]};
     for (int j = n - 1; j >= 0; j--) {

@@ -1,0 +1,286 @@
+// Device-side math of the rasterizer: per-Gaussian geometry, projection of
+// one Gaussian into one view, the SH colour, the per-pair compositing step
+// and wavefront reductions.  Everything per Gaussian-view runs in float64
+// (MI355X executes FP64 vector math at half the FP32 rate, and the projected
+// mean must be exact to ~1e-6 px at city-scale coordinates); everything per
+// (pixel, Gaussian) pair runs in float32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gsr_internal.h"
+
+namespace gsr {
+
+// ------------------------------------------------------------ camera, geometry
+
+struct Cam64 {
+  double R[9], t[3], fx, fy, cx, cy;
+  int W, H;
+};
+
+__device__ __forceinline__ Cam64 cam64(const gsr_camera &c, int W, int H) {
+  Cam64 k;
+#pragma unroll
+  for (int a = 0; a < 9; a++) k.R[a] = (double)c.R[a];
+#pragma unroll
+  for (int a = 0; a < 3; a++) k.t[a] = (double)c.t[a];
+  k.fx = c.fx;
+  k.fy = c.fy;
+  k.cx = c.cx;
+  k.cy = c.cy;
+  k.W = W;
+  k.H = H;
+  return k;
+}
+
+// View-independent part of one Gaussian.
+struct Geo {
+  double mu[3];
+  double s[3];   // exp(log_scale)
+  double q[4];   // unit quaternion (w, x, y, z)
+  double qn;     // |q_raw|
+  double Rq[9];  // rotation of q, row major
+  double Sig[6]; // covariance, symmetric: xx xy xz yy yz zz
+  double opac;
+};
+
+__device__ __forceinline__ void rot_of_quat(const double q[4], double Rq[9]) {
+  // R = (w^2 - |v|^2) I + 2 v v^T + 2 w [v]x   for the unit quaternion (w, v)
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  const double d = w * w - (x * x + y * y + z * z);
+  Rq[0] = d + 2 * x * x;   Rq[1] = 2 * x * y - 2 * w * z; Rq[2] = 2 * x * z + 2 * w * y;
+  Rq[3] = 2 * y * x + 2 * w * z; Rq[4] = d + 2 * y * y;   Rq[5] = 2 * y * z - 2 * w * x;
+  Rq[6] = 2 * z * x - 2 * w * y; Rq[7] = 2 * z * y + 2 * w * x; Rq[8] = d + 2 * z * z;
+}
+
+__device__ __forceinline__ void load_geo(const KParams &p, int64_t i, Geo &g) {
+  const int64_t n = p.n;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    g.mu[a] = (double)p.means[a * n + i];
+    g.s[a] = exp((double)p.log_scales[a * n + i]);
+  }
+  double qr[4];
+#pragma unroll
+  for (int a = 0; a < 4; a++) qr[a] = (double)p.quats[a * n + i];
+  g.qn = sqrt(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+  const double inv = 1.0 / g.qn;
+#pragma unroll
+  for (int a = 0; a < 4; a++) g.q[a] = qr[a] * inv;
+  rot_of_quat(g.q, g.Rq);
+  // Sigma = Rq diag(s^2) Rq^T
+  const double s2[3] = {g.s[0] * g.s[0], g.s[1] * g.s[1], g.s[2] * g.s[2]};
+  const int idx[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+#pragma unroll
+  for (int e = 0; e < 6; e++) {
+    const int r = idx[e][0], c = idx[e][1];
+    g.Sig[e] = g.Rq[r * 3 + 0] * s2[0] * g.Rq[c * 3 + 0] + g.Rq[r * 3 + 1] * s2[1] * g.Rq[c * 3 + 1] +
+               g.Rq[r * 3 + 2] * s2[2] * g.Rq[c * 3 + 2];
+  }
+  g.opac = 1.0 / (1.0 + exp(-(double)p.logits[i]));
+}
+
+__device__ __forceinline__ double sig_at(const double S[6], int r, int c) {
+  const int m = r < c ? r * 3 - (r * (r + 1)) / 2 + c : c * 3 - (c * (c + 1)) / 2 + r;
+  return S[m];
+}
+
+// Projection of one Gaussian into one view.
+struct Proj {
+  double tc[3];
+  double mx, my;
+  double u, v;       // x/z, y/z as used inside J (clamped)
+  bool cu, cv;       // clamp active
+  double T0[3], T1[3];  // rows of J W
+  double a, b, c, det;  // dilated 2D covariance
+  double A, B, C;       // conic
+  int x0, y0, x1, y1;   // inclusive tile rectangle
+};
+
+// Returns true when the Gaussian is visible (depth inside (near, far),
+// positive-definite 2D covariance, non-empty tile rectangle).
+__device__ __forceinline__ bool project_view(const Geo &g, const Cam64 &k, const KOpts &o, int tiles_x,
+                                             int tiles_y, Proj &P) {
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+    P.tc[r] = k.R[r * 3 + 0] * g.mu[0] + k.R[r * 3 + 1] * g.mu[1] + k.R[r * 3 + 2] * g.mu[2] + k.t[r];
+  const double tz = P.tc[2];
+  if (!(tz > (double)o.near_plane && tz < (double)o.far_plane)) return false;
+  const double iz = 1.0 / tz;
+  const double ux = P.tc[0] * iz, uy = P.tc[1] * iz;
+  P.mx = k.fx * ux + k.cx;
+  P.my = k.fy * uy + k.cy;
+  const double limx = (double)o.jac_clamp * (0.5 * k.W / k.fx);
+  const double limy = (double)o.jac_clamp * (0.5 * k.H / k.fy);
+  P.cu = fabs(ux) > limx;
+  P.cv = fabs(uy) > limy;
+  P.u = P.cu ? copysign(limx, ux) : ux;
+  P.v = P.cv ? copysign(limy, uy) : uy;
+  // J = [[fx/z, 0, -fx u / z], [0, fy/z, -fy v / z]];  T = J W
+  const double j00 = k.fx * iz, j02 = -k.fx * P.u * iz, j11 = k.fy * iz, j12 = -k.fy * P.v * iz;
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    P.T0[c] = j00 * k.R[c] + j02 * k.R[6 + c];
+    P.T1[c] = j11 * k.R[3 + c] + j12 * k.R[6 + c];
+  }
+  double ST0[3], ST1[3];
+#pragma unroll
+  for (int r = 0; r < 3; r++) {
+    ST0[r] = sig_at(g.Sig, r, 0) * P.T0[0] + sig_at(g.Sig, r, 1) * P.T0[1] + sig_at(g.Sig, r, 2) * P.T0[2];
+    ST1[r] = sig_at(g.Sig, r, 0) * P.T1[0] + sig_at(g.Sig, r, 1) * P.T1[1] + sig_at(g.Sig, r, 2) * P.T1[2];
+  }
+  P.a = P.T0[0] * ST0[0] + P.T0[1] * ST0[1] + P.T0[2] * ST0[2] + (double)o.eps2d;
+  P.b = P.T0[0] * ST1[0] + P.T0[1] * ST1[1] + P.T0[2] * ST1[2];
+  P.c = P.T1[0] * ST1[0] + P.T1[1] * ST1[1] + P.T1[2] * ST1[2] + (double)o.eps2d;
+  P.det = P.a * P.c - P.b * P.b;
+  if (!(P.det > 0.0)) return false;
+  const double idet = 1.0 / P.det;
+  P.A = P.c * idet;
+  P.B = -P.b * idet;
+  P.C = P.a * idet;
+  const double hd = 0.5 * (P.a - P.c);
+  const double lam = 0.5 * (P.a + P.c) + sqrt(hd * hd + P.b * P.b);
+  const double rad = ceil((double)o.sigma * sqrt(lam));
+  const double lox = floor((P.mx - rad) / o.tile_w), hix = floor((P.mx + rad) / o.tile_w);
+  const double loy = floor((P.my - rad) / o.tile_h), hiy = floor((P.my + rad) / o.tile_h);
+  if (hix < 0.0 || hiy < 0.0 || lox > tiles_x - 1 || loy > tiles_y - 1) return false;
+  P.x0 = lox < 0.0 ? 0 : (int)lox;
+  P.y0 = loy < 0.0 ? 0 : (int)loy;
+  P.x1 = hix > tiles_x - 1 ? tiles_x - 1 : (int)hix;
+  P.y1 = hiy > tiles_y - 1 ? tiles_y - 1 : (int)hiy;
+  return true;
+}
+
+// --------------------------------------------------------- spherical harmonics
+// Real orthonormal SH with the Condon-Shortley phase, index l*l + l + m.
+// The polynomials below agree with the textbook functions on the unit sphere;
+// their gradients are only ever used projected onto the tangent plane.
+constexpr double kY0 = 0.28209479177387814;   // 1/(2 sqrt(pi))
+constexpr double kY1 = 0.48860251190291992;   // sqrt(3/(4 pi))
+constexpr double kY2a = 1.0925484305920792;   // sqrt(15/pi)/2
+constexpr double kY2b = 0.31539156525252005;  // sqrt(5/pi)/4
+constexpr double kY2c = 0.54627421529603959;  // sqrt(15/pi)/4
+constexpr double kY3a = 0.59004358992664352;  // sqrt(35/(2 pi))/4
+constexpr double kY3b = 2.8906114426405538;   // sqrt(105/pi)/2
+constexpr double kY3c = 0.45704579946446572;  // sqrt(21/(2 pi))/4
+constexpr double kY3d = 0.37317633259011540;  // sqrt(7/pi)/4
+constexpr double kY3e = 1.4453057213202769;   // sqrt(105/pi)/4
+
+template <int D>
+__device__ __forceinline__ void sh_eval(double x, double y, double z, double *Y) {
+  Y[0] = kY0;
+  if (D >= 1) {
+    Y[1] = -kY1 * y;
+    Y[2] = kY1 * z;
+    Y[3] = -kY1 * x;
+  }
+  if (D >= 2) {
+    const double xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = kY2a * x * y;
+    Y[5] = -kY2a * y * z;
+    Y[6] = kY2b * (2.0 * zz - xx - yy);
+    Y[7] = -kY2a * x * z;
+    Y[8] = kY2c * (xx - yy);
+    if (D >= 3) {
+      Y[9] = -kY3a * y * (3.0 * xx - yy);
+      Y[10] = kY3b * x * y * z;
+      Y[11] = -kY3c * y * (4.0 * zz - xx - yy);
+      Y[12] = kY3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+      Y[13] = -kY3c * x * (4.0 * zz - xx - yy);
+      Y[14] = kY3e * z * (xx - yy);
+      Y[15] = -kY3a * x * (xx - 3.0 * yy);
+    }
+  }
+}
+
+// Gradient w.r.t. (x, y, z) of sum_k w_k Y_k (polynomial forms above).
+template <int D>
+__device__ __forceinline__ void sh_grad(double x, double y, double z, const double *w, double g[3]) {
+  g[0] = g[1] = g[2] = 0.0;
+  if (D >= 1) {
+    g[1] += -kY1 * w[1];
+    g[2] += kY1 * w[2];
+    g[0] += -kY1 * w[3];
+  }
+  if (D >= 2) {
+    g[0] += kY2a * y * w[4];
+    g[1] += kY2a * x * w[4];
+    g[1] += -kY2a * z * w[5];
+    g[2] += -kY2a * y * w[5];
+    g[0] += -2.0 * kY2b * x * w[6];
+    g[1] += -2.0 * kY2b * y * w[6];
+    g[2] += 4.0 * kY2b * z * w[6];
+    g[0] += -kY2a * z * w[7];
+    g[2] += -kY2a * x * w[7];
+    g[0] += 2.0 * kY2c * x * w[8];
+    g[1] += -2.0 * kY2c * y * w[8];
+    if (D >= 3) {
+      const double xx = x * x, yy = y * y, zz = z * z;
+      g[0] += -kY3a * 6.0 * x * y * w[9];
+      g[1] += -kY3a * (3.0 * xx - 3.0 * yy) * w[9];
+      g[0] += kY3b * y * z * w[10];
+      g[1] += kY3b * x * z * w[10];
+      g[2] += kY3b * x * y * w[10];
+      g[0] += kY3c * 2.0 * x * y * w[11];
+      g[1] += -kY3c * (4.0 * zz - xx - 3.0 * yy) * w[11];
+      g[2] += -kY3c * 8.0 * y * z * w[11];
+      g[0] += -kY3d * 6.0 * x * z * w[12];
+      g[1] += -kY3d * 6.0 * y * z * w[12];
+      g[2] += kY3d * (6.0 * zz - 3.0 * xx - 3.0 * yy) * w[12];
+      g[0] += -kY3c * (4.0 * zz - 3.0 * xx - yy) * w[13];
+      g[1] += kY3c * 2.0 * x * y * w[13];
+      g[2] += -kY3c * 8.0 * x * z * w[13];
+      g[0] += kY3e * 2.0 * x * z * w[14];
+      g[1] += -kY3e * 2.0 * y * z * w[14];
+      g[2] += kY3e * (xx - yy) * w[14];
+      g[0] += -kY3a * (3.0 * xx - 3.0 * yy) * w[15];
+      g[1] += kY3a * 6.0 * x * y * w[15];
+    }
+  }
+}
+
+// ------------------------------------------------------------ per-pair step
+// The alpha of one (pixel, record) pair.  Written with explicit fused
+// multiply-adds so that the forward and the reverse kernels evaluate the
+// identical float32 expression and replay the same skip / stop decisions.
+struct PairAlpha {
+  float dx, dy, G, raw, alpha;
+};
+
+__device__ __forceinline__ PairAlpha pair_alpha(float pxc, float pyc, const float4 &r0, const float4 &r1,
+                                                float alpha_max) {
+  PairAlpha a;
+  a.dx = (pxc - r0.x) - r0.z;
+  a.dy = (pyc - r0.y) - r0.w;
+  // p = -(A dx^2 + C dy^2) / 2 - B dx dy
+  const float quad = __fmaf_rn(r1.x * a.dx, a.dx, r1.z * a.dy * a.dy);
+  const float p = __fmaf_rn(-0.5f, quad, -(r1.y * a.dx * a.dy));
+  a.G = p > 0.0f ? -1.0f : expf(p);  // G < 0 marks "skip: p > 0"
+  a.raw = r1.w * a.G;
+  a.alpha = fminf(alpha_max, a.raw);
+  return a;
+}
+
+// ------------------------------------------------------- wavefront reduction
+
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ __forceinline__ float dpp_or_zero(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK,
+                                                               BANK_MASK, false));
+}
+
+// Sum over the 64 lanes of a wavefront; the total is valid in lane 63.
+__device__ __forceinline__ float wave_sum_lane63(float x) {
+  x += dpp_or_zero<0xB1>(x);       // quad_perm [1,0,3,2]
+  x += dpp_or_zero<0x4E>(x);       // quad_perm [2,3,0,1]
+  x += dpp_or_zero<0x141>(x);      // row_half_mirror
+  x += dpp_or_zero<0x140>(x);      // row_mirror
+  x += dpp_or_zero<0x142, 0xa>(x); // row_bcast:15 into rows 1 and 3
+  x += dpp_or_zero<0x143, 0xc>(x); // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+}  // namespace gsr

@@ -1,0 +1,117 @@
+// Internal types shared by the host orchestration and the HIP kernels.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gsr.h"
+
+namespace gsr {
+
+// One view of the plan as the kernels see it (copied into the workspace by
+// the set-up kernel of every step).
+struct ViewInfo {
+  int32_t W, H, tiles_x, tiles_y;
+  int64_t tile_base;  // first global tile id of the view
+  int64_t pix_base;   // first pixel of the view in the packed [3][H][W] images (in floats / 3)
+  float loss_scale;   // 1 / (3 H W n_views)
+  int32_t pad[3];
+};
+
+struct ViewTable {
+  ViewInfo v[GSR_MAX_VIEWS];
+  int32_t n_views;
+  int32_t pad[3];
+};
+
+// Device-side header at the start of the workspace.
+struct WsHeader {
+  uint32_t overflow;
+  uint32_t nonfinite;
+  uint32_t queue;         // persistent raster work counter
+  uint32_t union_count;   // Gaussians visible in >= 1 view
+  uint32_t isect_total;
+  uint32_t pad[3];
+  uint32_t isect[GSR_MAX_VIEWS];
+  uint32_t visible[GSR_MAX_VIEWS];
+};
+
+// Rasterizer constants as kernel arguments.
+struct KOpts {
+  float near_plane, far_plane, eps2d, sigma, jac_clamp, alpha_min, alpha_max, T_min;
+  float bg[3];
+  float stat_scale;
+  int32_t tile_w, tile_h;
+  int32_t check_finite;
+  int32_t accumulate;
+};
+
+struct KParams {
+  const float *means, *log_scales, *quats, *logits, *sh;
+  const uint8_t *keep;
+  int64_t n;
+  int32_t sh_degree;
+  int32_t n_views;
+};
+
+struct KGrads {
+  float *means, *log_scales, *quats, *logits, *sh;
+};
+
+// Record of one (view, Gaussian) pair, 64 bytes (4 x float4):
+//   r0 = mean2d as float pairs (hi x, hi y, lo x, lo y): mean = hi + lo
+//   r1 = conic (A, B, C), opacity
+//   r2 = colour (r, g, b), depth (camera z)
+//   r3 = rect (x0 | y0 << 16, x1 | y1 << 16), tiles touched, unused
+constexpr int kRecordFloat4 = 4;
+// 2D gradient of one record: dmean (2), dconic (3), dopacity, dcolour (3), padded to 12 floats.
+constexpr int kGrad2dStride = 12;
+
+struct KWs {
+  WsHeader *hdr;
+  ViewInfo *views;
+  uint32_t *view_bits;
+  float *records;   // [vn][16]
+  float *grad2d;    // [vn][12]
+  uint32_t *tile_count, *tile_start, *tile_fill;
+  float *tile_loss;
+  uint32_t *tile_order;
+  uint64_t *keys, *keys_alt;
+  float *pix_T;
+  uint32_t *pix_last;
+  float *pix_dLdC;
+  float *history;
+  int64_t vn, tiles_total, pixels_total, capacity, history_entries;
+};
+
+// ---------------------------------------------------------------- launchers
+// Defined in gsr_kernels.hip; every launcher enqueues on `stream` and returns
+// the launch's hipError_t as int.
+
+int launch_setup(const ViewTable &table, const KWs &ws, int64_t zero_tiles_from, int64_t zero_tiles_count,
+                 int zero_view_bits, int64_t n, void *stream);
+int launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, void *stream);
+int launch_fill_f32(float *p, float value, int64_t count, void *stream);
+int launch_project(const KParams &p, const gsr_camera *cams, const KOpts &o, const KWs &ws, int view_lo,
+                   int view_hi, int or_bits, void *stream);
+int launch_scan(const KWs &ws, int64_t tile_lo, int64_t tile_hi, int64_t base, int view_lo, int view_hi,
+                void *stream);
+int launch_emit(const KWs &ws, int64_t n, int n_views, int view_only, void *stream);
+int launch_sort(const KWs &ws, int64_t tile_lo, int64_t tile_count, void *stream);
+int launch_raster_fwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, float *images,
+                      int n_views, int store_history, int lds_batch, void *stream);
+int launch_l1(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *images,
+              const float *targets, int n_views, void *stream);
+int launch_raster_bwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *dLdC,
+                      int n_views, int use_history, int lds_batch, void *stream);
+int launch_fused(const KWs &ws, const KOpts &o, const float *targets, float *images, int n_views,
+                 int use_history, int lds_batch, int grid, void *stream);
+int launch_project_bwd(const KParams &p, const gsr_camera *cams, const KOpts &o, const KWs &ws,
+                       const KGrads &g, float *stat_S, uint32_t *stat_n, int view_only, void *stream);
+int launch_loss(const KWs &ws, int n_views, float *loss, void *stream);
+int launch_visibility(const KParams &p, const gsr_camera *cams, const KOpts &o, const KWs &ws,
+                      const float *aabb6, uint32_t *bits, uint8_t *keep_out, uint8_t *in_block,
+                      void *stream);
+int launch_copy_pixels(const KWs &ws, float *T_out, uint32_t *last_out, void *stream);
+
+}  // namespace gsr

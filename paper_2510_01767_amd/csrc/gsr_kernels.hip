@@ -1,0 +1,1073 @@
+// HIP kernels of the differentiable Gaussian rasterizer for gfx950 (MI355X).
+//
+// Step structure (one training step of a block, Sec. 3 / App. A.1):
+//   setup        view table + counters into the workspace (graph-safe: no memset nodes)
+//   project      per Gaussian, all requested views: cull, EWA projection, SH colour,
+//                64-byte record, per-tile intersection counts (device atomics)
+//   scan         exclusive scan of the per-tile counts -> tile ranges, overflow flag
+//   emit         per visible record, one 64-bit key (fp32 depth bits << 32 | record)
+//                per covered tile, scattered into its tile's bucket
+//   sort         per tile, order the bucket by key in LDS (bitonic; merge passes for
+//                buckets larger than one LDS load)
+//   raster       per tile, front-to-back compositing (Sec. 3.2 blending sum)
+//   l1 / bwd     L1 gradient, back-to-front reverse compositing with wave-level
+//                reductions and one atomic per (tile, record, component)
+//   fused        persistent kernel: forward + L1 + reverse per tile, work queue
+//   project_bwd  per Gaussian, all views: chain rule to the raw parameters and the
+//                densification statistics (Sec. 3.3)
+//
+// No kernel waits on another workgroup; persistent kernels take work from an
+// atomic counter and exit when it runs past the last tile.
+#include <hip/hip_runtime.h>
+
+#include "gsr_device.h"
+
+namespace gsr {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ const float4 *rec_ptr(const KWs &ws, int64_t r) {
+  return reinterpret_cast<const float4 *>(ws.records) + r * kRecordFloat4;
+}
+
+// Global tile id -> view (linear search over at most 32 views).
+__device__ __forceinline__ int view_of_tile(const ViewInfo *views, int n_views, int64_t t) {
+  int v = 0;
+  while (v + 1 < n_views && views[v + 1].tile_base <= t) v++;
+  return v;
+}
+
+// Spread consecutive tiles of a grid over one XCD: blocks are dispatched to
+// the 8 XCDs round-robin, so block b runs on XCD b % 8; give that XCD the
+// contiguous chunk [xcd * per, (xcd + 1) * per) so neighbouring tiles (which
+// share Gaussians) hit the same L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t count) {
+  const int64_t per = (count + 7) / 8;
+  return (b % 8) * per + b / 8;
+}
+
+__host__ __device__ __forceinline__ int64_t xcd_grid(int64_t count) { return ((count + 7) / 8) * 8; }
+
+// ------------------------------------------------------------------ set-up
+
+__global__ void k_setup(ViewTable table, KWs ws, int64_t zlo, int64_t zcount, int zero_bits, int64_t n) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (gid < table.n_views) ws.views[gid] = table.v[gid];
+  if (gid == 0) {
+    WsHeader *h = ws.hdr;
+    h->overflow = 0;
+    h->nonfinite = 0;
+    h->queue = 0;
+    h->union_count = 0;
+    h->isect_total = 0;
+  }
+  if (gid < GSR_MAX_VIEWS) {
+    ws.hdr->isect[gid] = 0;
+    ws.hdr->visible[gid] = 0;
+  }
+  for (int64_t k = gid; k < zcount; k += stride) {
+    ws.tile_count[zlo + k] = 0;
+    ws.tile_fill[zlo + k] = 0;
+  }
+  if (zero_bits)
+    for (int64_t k = gid; k < n; k += stride) ws.view_bits[k] = 0;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t count) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = v;
+}
+
+__global__ void k_fill_f32(float *p, float v, int64_t count) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = v;
+}
+
+// ------------------------------------------------------------------ project
+
+__device__ __forceinline__ bool finite_params(const KParams &p, int64_t i) {
+  const int64_t n = p.n;
+  float acc = 0.0f;
+  for (int a = 0; a < 3; a++) acc += p.means[a * n + i] * 0.0f + p.log_scales[a * n + i] * 0.0f;
+  for (int a = 0; a < 4; a++) acc += p.quats[a * n + i] * 0.0f;
+  acc += p.logits[i] * 0.0f;
+  return acc == 0.0f;  // any Inf or NaN makes the product NaN
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera *cams, KOpts o, KWs ws,
+                                                    int view_lo, int view_hi, int or_bits) {
+  constexpr int K = (D + 1) * (D + 1);
+  __shared__ gsr_camera s_cam[GSR_MAX_VIEWS];
+  __shared__ ViewInfo s_view[GSR_MAX_VIEWS];
+  for (int v = threadIdx.x; v < p.n_views; v += blockDim.x) {
+    s_cam[v] = cams[v];
+    s_view[v] = ws.views[v];
+  }
+  __syncthreads();
+  const int64_t n = p.n;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  bool keep = valid && (p.keep == nullptr || p.keep[i] != 0);
+  if (keep && o.check_finite && !finite_params(p, i)) {
+    atomicOr(&ws.hdr->nonfinite, 1u);
+    keep = false;
+  }
+  Geo g;
+  if (keep) load_geo(p, i, g);
+  uint32_t bits = (valid && or_bits) ? ws.view_bits[i] : 0u;
+  bool sh_loaded = false;
+  float sh[3 * K];
+  double cc_dir[3];
+  for (int v = view_lo; v < view_hi; v++) {
+    const ViewInfo &vi = s_view[v];
+    const Cam64 cam = cam64(s_cam[v], vi.W, vi.H);
+    Proj P;
+    const bool vis = keep && project_view(g, cam, o, vi.tiles_x, vi.tiles_y, P);
+    const uint64_t bal = __ballot(vis);
+    if (lane_id() == 0 && bal) atomicAdd(&ws.hdr->visible[v], (uint32_t)__popcll(bal));
+    if (!vis) continue;
+    bits |= 1u << v;
+    if (!sh_loaded) {
+#pragma unroll
+      for (int k = 0; k < 3 * K; k++) sh[k] = p.sh[(int64_t)k * n + i];
+      sh_loaded = true;
+    }
+    // colour: SH in the direction from the camera centre c = -R^T t to the mean
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+      cc_dir[a] = g.mu[a] + (cam.R[a] * cam.t[0] + cam.R[3 + a] * cam.t[1] + cam.R[6 + a] * cam.t[2]);
+    const double dn = sqrt(cc_dir[0] * cc_dir[0] + cc_dir[1] * cc_dir[1] + cc_dir[2] * cc_dir[2]);
+    const double x = cc_dir[0] / dn, y = cc_dir[1] / dn, z = cc_dir[2] / dn;
+    double Y[K];
+    sh_eval<D>(x, y, z, Y);
+    float col[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) {
+      double acc = 0.5;
+#pragma unroll
+      for (int k = 0; k < K; k++) acc += (double)sh[k * 3 + ch] * Y[k];
+      col[ch] = acc > 0.0 ? (float)acc : 0.0f;
+    }
+    const int64_t r = (int64_t)v * n + i;
+    float4 *rec = reinterpret_cast<float4 *>(ws.records) + r * kRecordFloat4;
+    const float mxh = (float)P.mx, myh = (float)P.my;
+    rec[0] = make_float4(mxh, myh, (float)(P.mx - (double)mxh), (float)(P.my - (double)myh));
+    rec[1] = make_float4((float)P.A, (float)P.B, (float)P.C, (float)g.opac);
+    rec[2] = make_float4(col[0], col[1], col[2], (float)P.tc[2]);
+    const uint32_t ntiles = (uint32_t)((P.x1 - P.x0 + 1) * (P.y1 - P.y0 + 1));
+    uint4 r3 = make_uint4((uint32_t)P.x0 | ((uint32_t)P.y0 << 16), (uint32_t)P.x1 | ((uint32_t)P.y1 << 16), ntiles, 0u);
+    reinterpret_cast<uint4 *>(rec)[3] = r3;
+    float4 *g2 = reinterpret_cast<float4 *>(ws.grad2d + r * kGrad2dStride);
+    g2[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+    g2[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    g2[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int ty = P.y0; ty <= P.y1; ty++)
+      for (int tx = P.x0; tx <= P.x1; tx++)
+        atomicAdd(&ws.tile_count[vi.tile_base + (int64_t)ty * vi.tiles_x + tx], 1u);
+  }
+  if (valid) ws.view_bits[i] = bits;
+  const uint64_t anyv = __ballot(valid && bits != 0 && view_hi == p.n_views);
+  if (lane_id() == 0 && anyv) atomicAdd(&ws.hdr->union_count, (uint32_t)__popcll(anyv));
+}
+
+// --------------------------------------------------------------------- scan
+// One workgroup of 1024 threads scans tile_count[lo, hi) into tile_start
+// (absolute slots, starting at `base`), writes tile_start[hi], the per-view
+// intersection counts and the overflow flag.
+
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan(KWs ws, int64_t lo, int64_t hi, int64_t base,
+                                                        int view_lo, int view_hi) {
+  __shared__ uint64_t s_sum[kScanThreads];
+  const int tid = threadIdx.x;
+  const int64_t len = hi - lo;
+  const int64_t chunk = (len + kScanThreads - 1) / kScanThreads;
+  const int64_t a = lo + tid * chunk;
+  const int64_t b = min(hi, a + chunk);
+  uint64_t s = 0;
+  for (int64_t t = a; t < b; t++) s += ws.tile_count[t];
+  s_sum[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    uint64_t add = tid >= off ? s_sum[tid - off] : 0;
+    __syncthreads();
+    s_sum[tid] += add;
+    __syncthreads();
+  }
+  uint64_t run = (uint64_t)base + s_sum[tid] - s;
+  const uint64_t cap = (uint64_t)ws.capacity;
+  for (int64_t t = a; t < b; t++) {
+    ws.tile_start[t] = (uint32_t)min(run, cap);
+    run += ws.tile_count[t];
+  }
+  const uint64_t total = s_sum[kScanThreads - 1];
+  if (tid == 0) {
+    ws.tile_start[hi] = (uint32_t)min((uint64_t)base + total, cap);
+    if ((uint64_t)base + total > cap) ws.hdr->overflow = 1u;
+    ws.hdr->isect_total = (uint32_t)min((uint64_t)base + total, (uint64_t)0xffffffffu);
+  }
+  __syncthreads();
+  for (int v = view_lo + tid; v < view_hi; v += kScanThreads) {
+    const ViewInfo vi = ws.views[v];
+    uint64_t sv = 0;
+    // per-view count from the counts themselves (the clamped starts could hide it)
+    for (int64_t t = vi.tile_base; t < vi.tile_base + (int64_t)vi.tiles_x * vi.tiles_y; t++) sv += ws.tile_count[t];
+    ws.hdr->isect[v] = (uint32_t)min(sv, (uint64_t)0xffffffffu);
+  }
+}
+
+// --------------------------------------------------------------------- emit
+
+__global__ __launch_bounds__(kBlock) void k_emit(KWs ws, int64_t n, int n_views, int view_only) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t bits = ws.view_bits[i];
+  if (view_only >= 0) bits &= 1u << view_only;
+  while (bits) {
+    const int v = __ffs(bits) - 1;
+    bits &= bits - 1;
+    const int64_t r = (int64_t)v * n + i;
+    const float4 *rec = rec_ptr(ws, r);
+    const uint4 r3 = reinterpret_cast<const uint4 *>(rec)[3];
+    const float depth = rec[2].w;
+    const ViewInfo vi = ws.views[v];
+    const int x0 = r3.x & 0xffff, y0 = r3.x >> 16, x1 = r3.y & 0xffff, y1 = r3.y >> 16;
+    const uint64_t key = ((uint64_t)__float_as_uint(depth) << 32) | (uint64_t)(uint32_t)r;
+    for (int ty = y0; ty <= y1; ty++)
+      for (int tx = x0; tx <= x1; tx++) {
+        const int64_t t = vi.tile_base + (int64_t)ty * vi.tiles_x + tx;
+        const uint64_t slot = (uint64_t)ws.tile_start[t] + atomicAdd(&ws.tile_fill[t], 1u);
+        if (slot < (uint64_t)ws.capacity && slot < (uint64_t)ws.tile_start[t + 1]) ws.keys[slot] = key;
+      }
+  }
+}
+
+// --------------------------------------------------------------------- sort
+
+constexpr int kSortLds = 2048;
+
+__device__ void bitonic_lds(uint64_t *s, int n2) {
+  for (int k = 2; k <= n2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = s[i], b = s[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            s[i] = b;
+            s[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+__device__ __forceinline__ int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Merge two sorted runs A[0, la), B[0, lb) into out; output element k is
+// found by a co-rank binary search (keys are unique).
+__device__ void merge_runs(const uint64_t *A, int64_t la, const uint64_t *B, int64_t lb, uint64_t *out) {
+  for (int64_t k = threadIdx.x; k < la + lb; k += blockDim.x) {
+    int64_t lo = k > lb ? k - lb : 0, hi = k < la ? k : la;
+    while (lo < hi) {
+      const int64_t ia = (lo + hi) >> 1;
+      if (A[ia] < B[k - ia - 1]) lo = ia + 1;
+      else hi = ia;
+    }
+    const int64_t ia = lo, ib = k - lo;
+    const bool takeA = ib >= lb || (ia < la && A[ia] < B[ib]);
+    out[k] = takeA ? A[ia] : B[ib];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort(KWs ws, int64_t tile_lo, int64_t tile_count) {
+  __shared__ uint64_t s[kSortLds];
+  const int64_t b = xcd_remap(blockIdx.x, tile_count);
+  if (b >= tile_count) return;
+  const int64_t t = tile_lo + b;
+  const int64_t start = ws.tile_start[t];
+  const int64_t end = ws.tile_start[t + 1];
+  const int64_t n = end - start;
+  if (n <= 1) return;
+  uint64_t *keys = ws.keys + start;
+  for (int64_t c0 = 0; c0 < n; c0 += kSortLds) {
+    const int m = (int)min((int64_t)kSortLds, n - c0);
+    const int n2 = next_pow2(m);
+    for (int k = threadIdx.x; k < n2; k += blockDim.x) s[k] = k < m ? keys[c0 + k] : ~0ull;
+    __syncthreads();
+    bitonic_lds(s, n2);
+    for (int k = threadIdx.x; k < m; k += blockDim.x) keys[c0 + k] = s[k];
+    __syncthreads();
+  }
+  if (n <= kSortLds) return;
+  uint64_t *src = keys, *dst = ws.keys_alt + start;
+  for (int64_t w = kSortLds; w < n; w <<= 1) {
+    for (int64_t a = 0; a < n; a += 2 * w) {
+      const int64_t la = min(w, n - a);
+      const int64_t lb = min(w, max((int64_t)0, n - a - w));
+      merge_runs(src + a, la, src + a + la, lb, dst + a);
+    }
+    __syncthreads();
+    uint64_t *tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+  if (src != keys) {
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) keys[k] = src[k];
+  }
+}
+
+// ------------------------------------------------------------------ raster
+// Per-tile state and the two tile passes shared by the plain kernels and the
+// fused persistent kernel.  One thread per pixel, 256 pixels per tile.
+
+struct TileCtx {
+  int64_t t;        // global tile id
+  int v;            // view
+  ViewInfo vi;
+  int px, py;       // this thread's pixel
+  bool inside;
+  int64_t start, end;  // entry range [start, end) in keys
+  int64_t pix;      // pixel index within the view
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ void tile_ctx(const KWs &ws, const ViewInfo *views, int n_views, int64_t t, TileCtx &c) {
+  c.t = t;
+  c.v = view_of_tile(views, n_views, t);
+  c.vi = views[c.v];
+  const int64_t local = t - c.vi.tile_base;
+  const int tx = (int)(local % c.vi.tiles_x), ty = (int)(local / c.vi.tiles_x);
+  c.px = tx * TW + (int)(threadIdx.x % TW);
+  c.py = ty * TH + (int)(threadIdx.x / TW);
+  c.inside = c.px < c.vi.W && c.py < c.vi.H;
+  c.pix = (int64_t)c.py * c.vi.W + c.px;
+  c.start = ws.tile_start[t];
+  c.end = min((int64_t)ws.tile_start[t + 1], ws.capacity);
+  if (c.end < c.start) c.end = c.start;
+}
+
+struct LdsRec {
+  float4 r0, r1, r2;
+};
+
+// Front-to-back compositing of one tile.  Returns the colour, the final
+// transmittance and `last` (entries processed before the stop, or the list
+// length).  With hist != nullptr it stores, for every processed entry, the
+// transmittance in front of it (0 when the entry was skipped).
+template <int B>
+__device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsRec *s_rec,
+                                             float C[3], float &T, int &last, float *hist) {
+  const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
+  T = 1.0f;
+  C[0] = C[1] = C[2] = 0.0f;
+  bool done = !c.inside;
+  last = 0;
+  bool stopped = false;
+  for (int64_t b = c.start; b < c.end; b += B) {
+    if (__syncthreads_and(done)) break;
+    if (threadIdx.x < B && b + threadIdx.x < c.end) {
+      const uint32_t r = (uint32_t)ws.keys[b + threadIdx.x];
+      const float4 *rec = rec_ptr(ws, r);
+      s_rec[threadIdx.x].r0 = rec[0];
+      s_rec[threadIdx.x].r1 = rec[1];
+      s_rec[threadIdx.x].r2 = rec[2];
+    }
+    __syncthreads();
+    const int nb = (int)min((int64_t)B, c.end - b);
+    for (int j = 0; j < nb && !done; j++) {
+      const LdsRec &R = s_rec[j];
+      const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, o.alpha_max);
+      float Tin = 0.0f;
+      if (a.alpha >= o.alpha_min) {
+        const float Tn = T * (1.0f - a.alpha);
+        if (Tn < o.T_min) {
+          done = true;
+          stopped = true;
+          last = (int)(b + j - c.start);
+          break;
+        }
+        const float w = a.alpha * T;
+        C[0] = __fmaf_rn(w, R.r2.x, C[0]);
+        C[1] = __fmaf_rn(w, R.r2.y, C[1]);
+        C[2] = __fmaf_rn(w, R.r2.z, C[2]);
+        Tin = T;
+        T = Tn;
+      }
+      if (hist) hist[(b + j) * 256 + threadIdx.x] = Tin;
+    }
+  }
+  if (!stopped) last = c.inside ? (int)(c.end - c.start) : 0;
+}
+
+// Back-to-front reverse pass of one tile for one pixel state.  g: dL/dC_out.
+// T: final transmittance (recompute) - updated in place.  Writes one atomic
+// per non-zero (record, component) of the tile.
+template <int B>
+__device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsRec *s_rec,
+                                              uint32_t *s_idx, float (*s_part)[B][9], int *s_max, float T,
+                                              int last, const float g[3], const float *hist) {
+  const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
+  const int wave = threadIdx.x >> 6;
+  float S[3] = {T * o.bg[0], T * o.bg[1], T * o.bg[2]};
+  const bool active = c.inside && (g[0] != 0.0f || g[1] != 0.0f || g[2] != 0.0f);
+  if (threadIdx.x == 0) *s_max = 0;
+  __syncthreads();
+  if (active && last > 0) atomicMax(s_max, last);
+  __syncthreads();
+  const int64_t hi0 = c.start + *s_max;
+  for (int64_t hi = hi0; hi > c.start; hi -= B) {
+    const int64_t lo = max(c.start, hi - B);
+    const int nb = (int)(hi - lo);
+    __syncthreads();
+    if (threadIdx.x < nb) {
+      const uint32_t r = (uint32_t)ws.keys[lo + threadIdx.x];
+      const float4 *rec = rec_ptr(ws, r);
+      s_rec[threadIdx.x].r0 = rec[0];
+      s_rec[threadIdx.x].r1 = rec[1];
+      s_rec[threadIdx.x].r2 = rec[2];
+      s_idx[threadIdx.x] = r;
+    }
+    __syncthreads();
+    for (int jj = nb - 1; jj >= 0; jj--) {
+      const int64_t j = lo + jj;
+      float v[9];
+#pragma unroll
+      for (int k = 0; k < 9; k++) v[k] = 0.0f;
+      bool contrib = false;
+      if (active && (int)(j - c.start) < last) {
+        const LdsRec &R = s_rec[jj];
+        const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, o.alpha_max);
+        if (a.alpha >= o.alpha_min) {
+          const float om = 1.0f - a.alpha;
+          const float Ti = hist ? hist[j * 256 + threadIdx.x] : T / om;
+          const float wgt = a.alpha * Ti;
+          const float col[3] = {R.r2.x, R.r2.y, R.r2.z};
+          float dLda = 0.0f;
+#pragma unroll
+          for (int ch = 0; ch < 3; ch++) {
+            dLda += g[ch] * (Ti * col[ch] - S[ch] / om);
+            v[6 + ch] = g[ch] * wgt;
+            S[ch] = __fmaf_rn(wgt, col[ch], S[ch]);
+          }
+          if (a.raw < o.alpha_max) {
+            const float gp = dLda * a.alpha;  // dL/dp
+            v[5] = dLda * a.G;
+            v[0] = gp * __fmaf_rn(R.r1.x, a.dx, R.r1.y * a.dy);
+            v[1] = gp * __fmaf_rn(R.r1.y, a.dx, R.r1.z * a.dy);
+            v[2] = -0.5f * gp * a.dx * a.dx;
+            v[3] = -gp * a.dx * a.dy;
+            v[4] = -0.5f * gp * a.dy * a.dy;
+          }
+          contrib = true;
+          T = Ti;
+        }
+      }
+      if (__ballot(contrib) != 0ull) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) v[k] = wave_sum_lane63(v[k]);
+        if (lane_id() == 63)
+#pragma unroll
+          for (int k = 0; k < 9; k++) s_part[wave][jj][k] = v[k];
+      } else if (lane_id() == 63) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) s_part[wave][jj][k] = 0.0f;
+      }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nb * 9; idx += blockDim.x) {
+      const int e = idx / 9, k = idx - e * 9;
+      const float sum = s_part[0][e][k] + s_part[1][e][k] + s_part[2][e][k] + s_part[3][e][k];
+      if (sum != 0.0f) unsafeAtomicAdd(&ws.grad2d[(int64_t)s_idx[e] * kGrad2dStride + k], sum);
+    }
+  }
+}
+
+__device__ __forceinline__ float block_sum_fixed(float x, float *s_w) {
+  x = wave_sum_lane63(x);
+  if (lane_id() == 63) s_w[threadIdx.x >> 6] = x;
+  __syncthreads();
+  const float r = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+  __syncthreads();
+  return r;
+}
+
+template <int TW, int TH, int B>
+__global__ __launch_bounds__(kBlock) void k_raster_fwd(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
+                                                       float *images, int n_views, int store_history) {
+  __shared__ LdsRec s_rec[B];
+  __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
+  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
+  __syncthreads();
+  const int64_t b = xcd_remap(blockIdx.x, tile_count);
+  if (b >= tile_count) return;
+  TileCtx c;
+  tile_ctx<TW, TH>(ws, s_views, n_views, tile_lo + b, c);
+  float C[3], T;
+  int last;
+  tile_forward<B>(ws, o, c, s_rec, C, T, last, store_history ? ws.history : nullptr);
+  if (c.inside) {
+    const int64_t P = (int64_t)c.vi.W * c.vi.H;
+    float *img = images + c.vi.pix_base * 3;
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) img[ch * P + c.pix] = __fmaf_rn(T, o.bg[ch], C[ch]);
+    ws.pix_T[c.vi.pix_base + c.pix] = T;
+    ws.pix_last[c.vi.pix_base + c.pix] = (uint32_t)last;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_l1(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
+                                               const float *images, const float *targets, int n_views, int tw,
+                                               int th) {
+  __shared__ float s_w[4];
+  __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
+  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
+  __syncthreads();
+  const int64_t t = tile_lo + blockIdx.x;
+  const int v = view_of_tile(s_views, n_views, t);
+  const ViewInfo vi = s_views[v];
+  const int64_t local = t - vi.tile_base;
+  const int px = (int)(local % vi.tiles_x) * tw + (int)(threadIdx.x % tw);
+  const int py = (int)(local / vi.tiles_x) * th + (int)(threadIdx.x / tw);
+  float acc = 0.0f;
+  if (px < vi.W && py < vi.H) {
+    const int64_t P = (int64_t)vi.W * vi.H;
+    const int64_t base = vi.pix_base * 3 + (int64_t)py * vi.W + px;
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) {
+      const float d = images[base + ch * P] - targets[base + ch * P];
+      acc += fabsf(d);
+      ws.pix_dLdC[base + ch * P] = d > 0.0f ? vi.loss_scale : (d < 0.0f ? -vi.loss_scale : 0.0f);
+    }
+  }
+  const float s = block_sum_fixed(acc, s_w);
+  if (threadIdx.x == 0) ws.tile_loss[t] = s;
+}
+
+template <int TW, int TH, int B>
+__global__ __launch_bounds__(kBlock) void k_raster_bwd(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
+                                                       const float *dLdC, int n_views, int use_history) {
+  __shared__ LdsRec s_rec[B];
+  __shared__ uint32_t s_idx[B];
+  __shared__ float s_part[4][B][9];
+  __shared__ int s_max;
+  __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
+  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
+  __syncthreads();
+  const int64_t b = xcd_remap(blockIdx.x, tile_count);
+  if (b >= tile_count) return;
+  TileCtx c;
+  tile_ctx<TW, TH>(ws, s_views, n_views, tile_lo + b, c);
+  float g[3] = {0.f, 0.f, 0.f};
+  float T = 1.0f;
+  int last = 0;
+  if (c.inside) {
+    const int64_t P = (int64_t)c.vi.W * c.vi.H;
+    const float *d = dLdC + c.vi.pix_base * 3 + c.pix;
+    g[0] = d[0];
+    g[1] = d[P];
+    g[2] = d[2 * P];
+    T = ws.pix_T[c.vi.pix_base + c.pix];
+    last = (int)ws.pix_last[c.vi.pix_base + c.pix];
+  }
+  tile_backward<B>(ws, o, c, s_rec, s_idx, s_part, &s_max, T, last, g, use_history ? ws.history : nullptr);
+}
+
+// Persistent fused forward + L1 + reverse pass.  Workgroups take tiles from
+// ws.hdr->queue (in tile_order when given) until the counter passes the last
+// tile; no workgroup ever waits for another.
+template <int TW, int TH, int B>
+__global__ __launch_bounds__(kBlock) void k_fused(KWs ws, KOpts o, const float *targets, float *images,
+                                                  int n_views, int use_history, const uint32_t *order) {
+  __shared__ LdsRec s_rec[B];
+  __shared__ uint32_t s_idx[B];
+  __shared__ float s_part[4][B][9];
+  __shared__ int s_max;
+  __shared__ float s_w[4];
+  __shared__ int64_t s_item;
+  __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
+  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
+  float *hist = use_history ? ws.history : nullptr;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(&ws.hdr->queue, 1u);
+    __syncthreads();
+    const int64_t item = s_item;
+    if (item >= ws.tiles_total) break;
+    const int64_t t = order ? (int64_t)order[item] : item;
+    TileCtx c;
+    tile_ctx<TW, TH>(ws, s_views, n_views, t, c);
+    float C[3], T;
+    int last;
+    tile_forward<B>(ws, o, c, s_rec, C, T, last, hist);
+    float g[3] = {0.f, 0.f, 0.f};
+    float acc = 0.0f;
+    if (c.inside) {
+      const int64_t P = (int64_t)c.vi.W * c.vi.H;
+      const int64_t base = c.vi.pix_base * 3 + c.pix;
+#pragma unroll
+      for (int ch = 0; ch < 3; ch++) {
+        const float out = __fmaf_rn(T, o.bg[ch], C[ch]);
+        images[base + ch * P] = out;
+        const float d = out - targets[base + ch * P];
+        acc += fabsf(d);
+        g[ch] = d > 0.0f ? c.vi.loss_scale : (d < 0.0f ? -c.vi.loss_scale : 0.0f);
+      }
+      ws.pix_T[c.vi.pix_base + c.pix] = T;
+      ws.pix_last[c.vi.pix_base + c.pix] = (uint32_t)last;
+    }
+    const float s = block_sum_fixed(acc, s_w);
+    if (threadIdx.x == 0) ws.tile_loss[t] = s;
+    tile_backward<B>(ws, o, c, s_rec, s_idx, s_part, &s_max, T, last, g, hist);
+  }
+}
+
+// --------------------------------------------------------------- loss total
+
+__global__ __launch_bounds__(kBlock) void k_loss(KWs ws, int n_views, float *loss) {
+  __shared__ double s_acc[kBlock];
+  double total = 0.0;
+  for (int v = 0; v < n_views; v++) {
+    const ViewInfo vi = ws.views[v];
+    const int64_t nt = (int64_t)vi.tiles_x * vi.tiles_y;
+    double a = 0.0;
+    for (int64_t k = threadIdx.x; k < nt; k += blockDim.x) a += (double)ws.tile_loss[vi.tile_base + k];
+    s_acc[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) s_acc[threadIdx.x] += s_acc[threadIdx.x + off];
+      __syncthreads();
+    }
+    total += s_acc[0] * (double)vi.loss_scale;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = (float)total;
+}
+
+// -------------------------------------------------------------- project_bwd
+// Reverse mode of the projection for every view in which the Gaussian is
+// visible (view_only >= 0 restricts to one view and adds into the gradients).
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_project_bwd(KParams p, const gsr_camera *cams, KOpts o, KWs ws,
+                                                        KGrads gr, float *stat_S, uint32_t *stat_n,
+                                                        int view_only) {
+  constexpr int K = (D + 1) * (D + 1);
+  __shared__ gsr_camera s_cam[GSR_MAX_VIEWS];
+  __shared__ ViewInfo s_view[GSR_MAX_VIEWS];
+  for (int v = threadIdx.x; v < p.n_views; v += blockDim.x) {
+    s_cam[v] = cams[v];
+    s_view[v] = ws.views[v];
+  }
+  __syncthreads();
+  const int64_t n = p.n;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t bits = ws.view_bits[i];
+  if (view_only >= 0) bits &= 1u << view_only;
+  const bool add = view_only >= 0 || o.accumulate;
+  if (bits == 0) {
+    if (!add) {
+      for (int a = 0; a < 3; a++) gr.means[a * n + i] = 0.f, gr.log_scales[a * n + i] = 0.f;
+      for (int a = 0; a < 4; a++) gr.quats[a * n + i] = 0.f;
+      gr.logits[i] = 0.f;
+      for (int k = 0; k < 3 * K; k++) gr.sh[(int64_t)k * n + i] = 0.f;
+    }
+    return;
+  }
+  Geo g;
+  load_geo(p, i, g);
+  float sh[3 * K];
+#pragma unroll
+  for (int k = 0; k < 3 * K; k++) sh[k] = p.sh[(int64_t)k * n + i];
+  double gmu[3] = {0, 0, 0}, gSig[6] = {0, 0, 0, 0, 0, 0}, gopac = 0.0;
+  float gsh[3 * K];
+#pragma unroll
+  for (int k = 0; k < 3 * K; k++) gsh[k] = 0.f;
+  float Sacc = 0.f;
+  uint32_t cnt = 0;
+  const double stat_scale = o.stat_scale;
+  while (bits) {
+    const int v = __ffs(bits) - 1;
+    bits &= bits - 1;
+    const ViewInfo &vi = s_view[v];
+    const Cam64 cam = cam64(s_cam[v], vi.W, vi.H);
+    Proj P;
+    project_view(g, cam, o, vi.tiles_x, vi.tiles_y, P);  // visible by construction of view_bits
+    const float4 *g2 = reinterpret_cast<const float4 *>(ws.grad2d + ((int64_t)v * n + i) * kGrad2dStride);
+    const float4 q0 = g2[0], q1 = g2[1], q2 = g2[2];
+    const double gmx = q0.x, gmy = q0.y, gA = q0.z, gB = q0.w, gC = q1.x, go = q1.y;
+    const double gcol[3] = {q1.z, q1.w, q2.x};
+    Sacc += (float)(stat_scale * sqrt(gmx * gmx + gmy * gmy));
+    cnt += 1;
+    // colour -> SH coefficients and viewing direction
+    double d[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) d[a] = g.mu[a] + (cam.R[a] * cam.t[0] + cam.R[3 + a] * cam.t[1] + cam.R[6 + a] * cam.t[2]);
+    const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double x = d[0] / dn, y = d[1] / dn, z = d[2] / dn;
+    double Y[K];
+    sh_eval<D>(x, y, z, Y);
+    double wk[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) wk[k] = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) {
+      double raw = 0.5;
+#pragma unroll
+      for (int k = 0; k < K; k++) raw += (double)sh[k * 3 + ch] * Y[k];
+      const double gr_ch = raw > 0.0 ? gcol[ch] : 0.0;
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        gsh[k * 3 + ch] += (float)(gr_ch * Y[k]);
+        wk[k] += gr_ch * (double)sh[k * 3 + ch];
+      }
+    }
+    if (D > 0) {
+      double gd[3];
+      sh_grad<D>(x, y, z, wk, gd);
+      const double dot = gd[0] * x + gd[1] * y + gd[2] * z;
+      gmu[0] += (gd[0] - dot * x) / dn;
+      gmu[1] += (gd[1] - dot * y) / dn;
+      gmu[2] += (gd[2] - dot * z) / dn;
+    }
+    gopac += go;
+    // conic -> 2D covariance:  dL/dS = -Q G_Q Q with G_Q = [[gA, gB/2], [gB/2, gC]]
+    const double QA = P.A, QB = P.B, QC = P.C;
+    const double h = 0.5 * gB;
+    const double m00 = gA * QA + h * QB, m01 = gA * QB + h * QC;  // G_Q Q
+    const double m10 = h * QA + gC * QB, m11 = h * QB + gC * QC;
+    const double gs00 = -(QA * m00 + QB * m10);
+    const double gs01 = -(QA * m01 + QB * m11);
+    const double gs11 = -(QB * m01 + QC * m11);
+    // S = T Sigma T^T (T = J W, rows T0, T1):  dL/dSigma = T^T G_S T
+    const double *T0 = P.T0, *T1 = P.T1;
+    {
+      int e = 0;
+#pragma unroll
+      for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int cidx = r; cidx < 3; cidx++, e++) {
+          double val = T0[r] * gs00 * T0[cidx] + T0[r] * gs01 * T1[cidx] + T1[r] * gs01 * T0[cidx] +
+                       T1[r] * gs11 * T1[cidx];
+          gSig[e] += (r == cidx) ? val : 2.0 * val;  // off-diagonals stored once, used twice
+        }
+    }
+    // dL/dT = 2 G_S T Sigma
+    double ST0[3], ST1[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+      ST0[r] = sig_at(g.Sig, r, 0) * T0[0] + sig_at(g.Sig, r, 1) * T0[1] + sig_at(g.Sig, r, 2) * T0[2];
+      ST1[r] = sig_at(g.Sig, r, 0) * T1[0] + sig_at(g.Sig, r, 1) * T1[1] + sig_at(g.Sig, r, 2) * T1[2];
+    }
+    double GT0[3], GT1[3];
+#pragma unroll
+    for (int cidx = 0; cidx < 3; cidx++) {
+      GT0[cidx] = 2.0 * (gs00 * ST0[cidx] + gs01 * ST1[cidx]);
+      GT1[cidx] = 2.0 * (gs01 * ST0[cidx] + gs11 * ST1[cidx]);
+    }
+    // T = J W:  dL/dJ = dL/dT W^T
+    double gj00 = 0, gj02 = 0, gj11 = 0, gj12 = 0;
+#pragma unroll
+    for (int cidx = 0; cidx < 3; cidx++) {
+      gj00 += GT0[cidx] * cam.R[cidx];
+      gj02 += GT0[cidx] * cam.R[6 + cidx];
+      gj11 += GT1[cidx] * cam.R[3 + cidx];
+      gj12 += GT1[cidx] * cam.R[6 + cidx];
+    }
+    const double tx = P.tc[0], ty = P.tc[1], tz = P.tc[2];
+    const double iz = 1.0 / tz, iz2 = iz * iz;
+    double gt[3] = {0, 0, 0};
+    gt[2] += -gj00 * cam.fx * iz2 - gj11 * cam.fy * iz2;
+    if (P.cu) {
+      gt[2] += gj02 * cam.fx * P.u * iz2;
+    } else {
+      gt[0] += -gj02 * cam.fx * iz2;
+      gt[2] += gj02 * 2.0 * cam.fx * tx * iz2 * iz;
+    }
+    if (P.cv) {
+      gt[2] += gj12 * cam.fy * P.v * iz2;
+    } else {
+      gt[1] += -gj12 * cam.fy * iz2;
+      gt[2] += gj12 * 2.0 * cam.fy * ty * iz2 * iz;
+    }
+    // projected mean
+    gt[0] += gmx * cam.fx * iz;
+    gt[1] += gmy * cam.fy * iz;
+    gt[2] += -(gmx * cam.fx * tx + gmy * cam.fy * ty) * iz2;
+    // t = W mu + t_v
+#pragma unroll
+    for (int a = 0; a < 3; a++) gmu[a] += cam.R[a] * gt[0] + cam.R[3 + a] * gt[1] + cam.R[6 + a] * gt[2];
+  }
+  // Sigma = Rq diag(s^2) Rq^T  (gSig holds dL/dSigma_ij for i <= j, off-diagonals doubled)
+  double G[9];
+  {
+    const int idx[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+#pragma unroll
+    for (int e = 0; e < 6; e++) {
+      const int r = idx[e][0], cidx = idx[e][1];
+      const double val = r == cidx ? gSig[e] : 0.5 * gSig[e];
+      G[r * 3 + cidx] = val;
+      G[cidx * 3 + r] = val;
+    }
+  }
+  // dL/dM = 2 G M with M = Rq diag(s);  s_j = exp(l_j)
+  double gl[3], GR[9];
+#pragma unroll
+  for (int j = 0; j < 3; j++) {
+    double gs = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+      const double gm = 2.0 * (G[r * 3 + 0] * g.Rq[0 * 3 + j] + G[r * 3 + 1] * g.Rq[1 * 3 + j] + G[r * 3 + 2] * g.Rq[2 * 3 + j]) * g.s[j];
+      gs += gm * g.Rq[r * 3 + j];
+      GR[r * 3 + j] = gm * g.s[j];
+    }
+    gl[j] = gs * g.s[j];
+  }
+  // R = (w^2 - |v|^2) I + 2 v v^T + 2 w [v]x  ->  unit quaternion
+  const double w = g.q[0], qx = g.q[1], qy = g.q[2], qz = g.q[3];
+  const double tr = GR[0] + GR[4] + GR[8];
+  const double cw = -qz * GR[1] + qy * GR[2] + qz * GR[3] - qx * GR[5] - qy * GR[6] + qx * GR[7];
+  double gq[4];
+  gq[0] = 2.0 * w * tr + 2.0 * cw;
+  const double vv[3] = {qx, qy, qz};
+  const double cross_k[3] = {-GR[5] + GR[7], GR[2] - GR[6], -GR[1] + GR[3]};
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    const double sym = (GR[k * 3 + 0] + GR[0 * 3 + k]) * vv[0] + (GR[k * 3 + 1] + GR[1 * 3 + k]) * vv[1] +
+                       (GR[k * 3 + 2] + GR[2 * 3 + k]) * vv[2];
+    gq[1 + k] = -2.0 * vv[k] * tr + 2.0 * sym + 2.0 * w * cross_k[k];
+  }
+  const double gd = gq[0] * g.q[0] + gq[1] * g.q[1] + gq[2] * g.q[2] + gq[3] * g.q[3];
+  const double inv_qn = 1.0 / g.qn;
+  float outq[4];
+#pragma unroll
+  for (int a = 0; a < 4; a++) outq[a] = (float)((gq[a] - gd * g.q[a]) * inv_qn);
+  const float glogit = (float)(gopac * g.opac * (1.0 - g.opac));
+  if (add) {
+    for (int a = 0; a < 3; a++) {
+      gr.means[a * n + i] += (float)gmu[a];
+      gr.log_scales[a * n + i] += (float)gl[a];
+    }
+    for (int a = 0; a < 4; a++) gr.quats[a * n + i] += outq[a];
+    gr.logits[i] += glogit;
+#pragma unroll
+    for (int k = 0; k < 3 * K; k++) gr.sh[(int64_t)k * n + i] += gsh[k];
+  } else {
+    for (int a = 0; a < 3; a++) {
+      gr.means[a * n + i] = (float)gmu[a];
+      gr.log_scales[a * n + i] = (float)gl[a];
+    }
+    for (int a = 0; a < 4; a++) gr.quats[a * n + i] = outq[a];
+    gr.logits[i] = glogit;
+#pragma unroll
+    for (int k = 0; k < 3 * K; k++) gr.sh[(int64_t)k * n + i] = gsh[k];
+  }
+  if (stat_S) stat_S[i] += Sacc;
+  if (stat_n) stat_n[i] += cnt;
+}
+
+// -------------------------------------------------------------- visibility
+
+__global__ __launch_bounds__(kBlock) void k_visibility(KParams p, const gsr_camera *cams, KOpts o, KWs ws,
+                                                       float bx0, float by0, float bz0, float bx1, float by1,
+                                                       float bz1, uint32_t *bits_out, uint8_t *keep_out,
+                                                       uint8_t *in_block) {
+  __shared__ gsr_camera s_cam[GSR_MAX_VIEWS];
+  __shared__ ViewInfo s_view[GSR_MAX_VIEWS];
+  for (int v = threadIdx.x; v < p.n_views; v += blockDim.x) {
+    s_cam[v] = cams[v];
+    s_view[v] = ws.views[v];
+  }
+  __syncthreads();
+  const int64_t n = p.n;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool keep = p.keep == nullptr || p.keep[i] != 0;
+  uint32_t bits = 0;
+  if (keep) {
+    Geo g;
+    load_geo(p, i, g);
+    for (int v = 0; v < p.n_views; v++) {
+      const ViewInfo &vi = s_view[v];
+      Proj P;
+      if (project_view(g, cam64(s_cam[v], vi.W, vi.H), o, vi.tiles_x, vi.tiles_y, P)) bits |= 1u << v;
+    }
+  }
+  if (bits_out) bits_out[i] = bits;
+  if (keep_out) keep_out[i] = bits != 0 ? 1 : 0;
+  if (in_block) {
+    const float x = p.means[i], y = p.means[n + i], z = p.means[2 * n + i];
+    in_block[i] = (x >= bx0 && x < bx1 && y >= by0 && y < by1 && z >= bz0 && z < bz1) ? 1 : 0;
+  }
+}
+
+__global__ void k_copy_pixels(KWs ws, float *T_out, uint32_t *last_out) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ws.pixels_total;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    if (T_out) T_out[k] = ws.pix_T[k];
+    if (last_out) last_out[k] = ws.pix_last[k];
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline int grid_for(int64_t count, int block = kBlock) {
+  int64_t g = (count + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 1048576) g = 1048576;
+  return (int)g;
+}
+
+static inline int last_err() { return (int)hipGetLastError(); }
+
+int launch_setup(const ViewTable &table, const KWs &ws, int64_t zlo, int64_t zcount, int zero_bits, int64_t n,
+                 void *stream) {
+  int64_t work = zcount;
+  if (zero_bits && n > work) work = n;
+  if (work < GSR_MAX_VIEWS) work = GSR_MAX_VIEWS;
+  hipLaunchKernelGGL(k_setup, dim3(grid_for(work)), dim3(kBlock), 0, (hipStream_t)stream, table, ws, zlo, zcount,
+                     zero_bits, n);
+  return last_err();
+}
+
+int launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, void *stream) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count)), dim3(kBlock), 0, (hipStream_t)stream, p, value, count);
+  return last_err();
+}
+
+int launch_fill_f32(float *p, float value, int64_t count, void *stream) {
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(count)), dim3(kBlock), 0, (hipStream_t)stream, p, value, count);
+  return last_err();
+}
+
+int launch_project(const KParams &p, const gsr_camera *cams, const KOpts &o, const KWs &ws, int view_lo,
+                   int view_hi, int or_bits, void *stream) {
+  const dim3 grid(grid_for(p.n)), block(kBlock);
+  hipStream_t s = (hipStream_t)stream;
+  switch (p.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_project<0>, grid, block, 0, s, p, cams, o, ws, view_lo, view_hi, or_bits); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, grid, block, 0, s, p, cams, o, ws, view_lo, view_hi, or_bits); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, s, p, cams, o, ws, view_lo, view_hi, or_bits); break;
+    default: hipLaunchKernelGGL(k_project<3>, grid, block, 0, s, p, cams, o, ws, view_lo, view_hi, or_bits); break;
+  }
+  return last_err();
+}
+
+int launch_scan(const KWs &ws, int64_t lo, int64_t hi, int64_t base, int view_lo, int view_hi, void *stream) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, (hipStream_t)stream, ws, lo, hi, base, view_lo,
+                     view_hi);
+  return last_err();
+}
+
+int launch_emit(const KWs &ws, int64_t n, int n_views, int view_only, void *stream) {
+  hipLaunchKernelGGL(k_emit, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, ws, n, n_views, view_only);
+  return last_err();
+}
+
+int launch_sort(const KWs &ws, int64_t tile_lo, int64_t tile_count, void *stream) {
+  if (tile_count <= 0) return 0;
+  hipLaunchKernelGGL(k_sort, dim3((unsigned)xcd_grid(tile_count)), dim3(kBlock), 0, (hipStream_t)stream, ws,
+                     tile_lo, tile_count);
+  return last_err();
+}
+
+#define GSR_TILE_DISPATCH(TW_, TH_, CALL)                       \
+  if (o.tile_w == TW_ && o.tile_h == TH_) {                     \
+    if (lds_batch == 64) { constexpr int B = 64; CALL(TW_, TH_, B); }          \
+    else if (lds_batch == 128) { constexpr int B = 128; CALL(TW_, TH_, B); }   \
+    else { constexpr int B = 256; CALL(TW_, TH_, B); }                          \
+    return last_err();                                          \
+  }
+
+int launch_raster_fwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, float *images,
+                      int n_views, int store_history, int lds_batch, void *stream) {
+  if (tile_count <= 0) return 0;
+  const dim3 grid((unsigned)xcd_grid(tile_count)), block(kBlock);
+  hipStream_t s = (hipStream_t)stream;
+#define CALL_FWD(a, b_, B) \
+  hipLaunchKernelGGL((k_raster_fwd<a, b_, B>), grid, block, 0, s, ws, o, tile_lo, tile_count, images, n_views, store_history)
+  GSR_TILE_DISPATCH(16, 16, CALL_FWD)
+  GSR_TILE_DISPATCH(32, 8, CALL_FWD)
+  GSR_TILE_DISPATCH(8, 32, CALL_FWD)
+#undef CALL_FWD
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_l1(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *images,
+              const float *targets, int n_views, void *stream) {
+  if (tile_count <= 0) return 0;
+  hipLaunchKernelGGL(k_l1, dim3((unsigned)tile_count), dim3(kBlock), 0, (hipStream_t)stream, ws, o, tile_lo,
+                     tile_count, images, targets, n_views, o.tile_w, o.tile_h);
+  return last_err();
+}
+
+int launch_raster_bwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *dLdC,
+                      int n_views, int use_history, int lds_batch, void *stream) {
+  if (tile_count <= 0) return 0;
+  const dim3 grid((unsigned)xcd_grid(tile_count)), block(kBlock);
+  hipStream_t s = (hipStream_t)stream;
+#define CALL_BWD(a, b_, B) \
+  hipLaunchKernelGGL((k_raster_bwd<a, b_, B>), grid, block, 0, s, ws, o, tile_lo, tile_count, dLdC, n_views, use_history)
+  GSR_TILE_DISPATCH(16, 16, CALL_BWD)
+  GSR_TILE_DISPATCH(32, 8, CALL_BWD)
+  GSR_TILE_DISPATCH(8, 32, CALL_BWD)
+#undef CALL_BWD
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_fused(const KWs &ws, const KOpts &o, const float *targets, float *images, int n_views,
+                 int use_history, int lds_batch, int grid_blocks, void *stream) {
+  const dim3 grid((unsigned)grid_blocks), block(kBlock);
+  hipStream_t s = (hipStream_t)stream;
+  const uint32_t *order = nullptr;
+#define CALL_FUSED(a, b_, B) \
+  hipLaunchKernelGGL((k_fused<a, b_, B>), grid, block, 0, s, ws, o, targets, images, n_views, use_history, order)
+  GSR_TILE_DISPATCH(16, 16, CALL_FUSED)
+  GSR_TILE_DISPATCH(32, 8, CALL_FUSED)
+  GSR_TILE_DISPATCH(8, 32, CALL_FUSED)
+#undef CALL_FUSED
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_project_bwd(const KParams &p, const gsr_camera *cams, const KOpts &o, const KWs &ws, const KGrads &g,
+                       float *stat_S, uint32_t *stat_n, int view_only, void *stream) {
+  const dim3 grid(grid_for(p.n)), block(kBlock);
+  hipStream_t s = (hipStream_t)stream;
+  switch (p.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, block, 0, s, p, cams, o, ws, g, stat_S, stat_n, view_only); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, block, 0, s, p, cams, o, ws, g, stat_S, stat_n, view_only); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, block, 0, s, p, cams, o, ws, g, stat_S, stat_n, view_only); break;
+    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, block, 0, s, p, cams, o, ws, g, stat_S, stat_n, view_only); break;
+  }
+  return last_err();
+}
+
+int launch_loss(const KWs &ws, int n_views, float *loss, void *stream) {
+  hipLaunchKernelGGL(k_loss, dim3(1), dim3(kBlock), 0, (hipStream_t)stream, ws, n_views, loss);
+  return last_err();
+}
+
+int launch_visibility(const KParams &p, const gsr_camera *cams, const KOpts &o, const KWs &ws, const float *aabb6,
+                      uint32_t *bits, uint8_t *keep_out, uint8_t *in_block, void *stream) {
+  hipLaunchKernelGGL(k_visibility, dim3(grid_for(p.n)), dim3(kBlock), 0, (hipStream_t)stream, p, cams, o, ws,
+                     aabb6[0], aabb6[1], aabb6[2], aabb6[3], aabb6[4], aabb6[5], bits, keep_out, in_block);
+  return last_err();
+}
+
+int launch_copy_pixels(const KWs &ws, float *T_out, uint32_t *last_out, void *stream) {
+  hipLaunchKernelGGL(k_copy_pixels, dim3(grid_for(ws.pixels_total)), dim3(kBlock), 0, (hipStream_t)stream, ws, T_out,
+                     last_out);
+  return last_err();
+}
+
+}  // namespace gsr
