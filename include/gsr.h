@@ -220,9 +220,11 @@ gsr_status gsr_graph_capture(gsr_plan *plan, const gsr_gaussians *g, const gsr_c
                              size_t ws_bytes, void *stream);
 gsr_status gsr_graph_launch(gsr_plan *plan, void *stream);
 
-/* Synchronises the stream and reads the counts of the last step from the
- * workspace.  Returns GSR_ERR_CAPACITY / GSR_ERR_NONFINITE when the
- * corresponding flag is set (counts are still filled in). */
+/* Counts of the last step: enqueues a small kernel that derives the visible
+ * counts from the view masks in the workspace (writing the workspace header),
+ * synchronises the stream and reads the header.  Returns GSR_ERR_CAPACITY /
+ * GSR_ERR_NONFINITE when the corresponding flag is set (counts are still
+ * filled in). */
 gsr_status gsr_query_counts(gsr_plan *plan, const void *ws, gsr_counts *counts, void *stream);
 
 /* Times the batched fused step for each candidate (tile shape 16x16, 32x8,

@@ -663,6 +663,9 @@ gsr_status gsr_graph_launch(gsr_plan *plan, void *stream) {
 
 gsr_status gsr_query_counts(gsr_plan *plan, const void *ws, gsr_counts *c, void *stream) {
   if (!plan || !ws || !c) return GSR_ERR_INVALID_ARG;
+  // visible counts are derived from the view masks on demand (see k_count_visible)
+  HIPCHK(launch_count_visible(ws_view(*plan, const_cast<void *>(ws)), plan->prob.n, plan->prob.n_views, stream),
+         "count visible");
   HIPCHK(hipStreamSynchronize((hipStream_t)stream), "sync");
   WsHeader h;
   HIPCHK(hipMemcpy(&h, (const char *)ws + plan->layout.header, sizeof h, hipMemcpyDeviceToHost), "read counts");

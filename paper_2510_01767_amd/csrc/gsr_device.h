@@ -54,31 +54,53 @@ __device__ __forceinline__ void rot_of_quat(const double q[4], double Rq[9]) {
   Rq[6] = 2 * z * x - 2 * w * y; Rq[7] = 2 * z * y + 2 * w * x; Rq[8] = d + 2 * z * z;
 }
 
-__device__ __forceinline__ void load_geo(const KParams &p, int64_t i, Geo &g) {
+// Activations and the 3D covariance of Gaussian i.  Both the forward (lean
+// GeoF) and the reverse pass (full Geo) go through these helpers, so they
+// see bit-identical covariances.
+__device__ __forceinline__ void geo_core(const KParams &p, int64_t i, double mu[3], double s[3], double q[4],
+                                         double &qn, double Rq[9], double Sig[6], double &opac) {
   const int64_t n = p.n;
 #pragma unroll
   for (int a = 0; a < 3; a++) {
-    g.mu[a] = (double)p.means[a * n + i];
-    g.s[a] = exp((double)p.log_scales[a * n + i]);
+    mu[a] = (double)p.means[a * n + i];
+    s[a] = exp((double)p.log_scales[a * n + i]);
   }
   double qr[4];
 #pragma unroll
   for (int a = 0; a < 4; a++) qr[a] = (double)p.quats[a * n + i];
-  g.qn = sqrt(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
-  const double inv = 1.0 / g.qn;
+  qn = sqrt(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+  const double inv = 1.0 / qn;
 #pragma unroll
-  for (int a = 0; a < 4; a++) g.q[a] = qr[a] * inv;
-  rot_of_quat(g.q, g.Rq);
+  for (int a = 0; a < 4; a++) q[a] = qr[a] * inv;
+  rot_of_quat(q, Rq);
   // Sigma = Rq diag(s^2) Rq^T
-  const double s2[3] = {g.s[0] * g.s[0], g.s[1] * g.s[1], g.s[2] * g.s[2]};
+  const double s2[3] = {s[0] * s[0], s[1] * s[1], s[2] * s[2]};
   const int idx[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
 #pragma unroll
   for (int e = 0; e < 6; e++) {
     const int r = idx[e][0], c = idx[e][1];
-    g.Sig[e] = g.Rq[r * 3 + 0] * s2[0] * g.Rq[c * 3 + 0] + g.Rq[r * 3 + 1] * s2[1] * g.Rq[c * 3 + 1] +
-               g.Rq[r * 3 + 2] * s2[2] * g.Rq[c * 3 + 2];
+    Sig[e] = Rq[r * 3 + 0] * s2[0] * Rq[c * 3 + 0] + Rq[r * 3 + 1] * s2[1] * Rq[c * 3 + 1] +
+             Rq[r * 3 + 2] * s2[2] * Rq[c * 3 + 2];
   }
-  g.opac = 1.0 / (1.0 + exp(-(double)p.logits[i]));
+  opac = 1.0 / (1.0 + exp(-(double)p.logits[i]));
+}
+
+__device__ __forceinline__ void load_geo(const KParams &p, int64_t i, Geo &g) {
+  geo_core(p, i, g.mu, g.s, g.q, g.qn, g.Rq, g.Sig, g.opac);
+}
+
+// What the forward keeps per Gaussian across views.
+struct GeoF {
+  double mu[3];
+  double Sig[6];
+  double opac;
+  double smax2;  // largest eigenvalue of Sigma = max scale^2
+};
+
+__device__ __forceinline__ void load_geo_fwd(const KParams &p, int64_t i, GeoF &g) {
+  double s[3], q[4], qn, Rq[9];
+  geo_core(p, i, g.mu, s, q, qn, Rq, g.Sig, g.opac);
+  g.smax2 = fmax(fmax(s[0] * s[0], s[1] * s[1]), s[2] * s[2]);
 }
 
 __device__ __forceinline__ double sig_at(const double S[6], int r, int c) {
@@ -95,12 +117,37 @@ struct Proj {
   double T0[3], T1[3];  // rows of J W
   double a, b, c, det;  // dilated 2D covariance
   double A, B, C;       // conic
+  double lam;           // largest eigenvalue of the dilated 2D covariance
   int x0, y0, x1, y1;   // inclusive tile rectangle
 };
 
 // Returns true when the Gaussian is visible (depth inside (near, far),
 // positive-definite 2D covariance, non-empty tile rectangle).
-__device__ __forceinline__ bool project_view(const Geo &g, const Cam64 &k, const KOpts &o, int tiles_x,
+// Cheap conservative test: false only when the Gaussian is certainly not
+// visible.  lambda_max(J W Sigma W^T J^T) <= |J|_F^2 max(s)^2, so the exact
+// tile rectangle lies inside the one built from this bound.
+__device__ __forceinline__ bool maybe_visible(const GeoF &g, const Cam64 &k, const KOpts &o, int tiles_x,
+                                              int tiles_y) {
+  double tc[3];
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+    tc[r] = k.R[r * 3 + 0] * g.mu[0] + k.R[r * 3 + 1] * g.mu[1] + k.R[r * 3 + 2] * g.mu[2] + k.t[r];
+  const double tz = tc[2];
+  if (!(tz > (double)o.near_plane && tz < (double)o.far_plane)) return false;
+  const double iz = 1.0 / tz;
+  const double ux = tc[0] * iz, uy = tc[1] * iz;
+  const double mx = k.fx * ux + k.cx, my = k.fy * uy + k.cy;
+  const double limx = (double)o.jac_clamp * (0.5 * k.W / k.fx);
+  const double limy = (double)o.jac_clamp * (0.5 * k.H / k.fy);
+  const double u = fmin(fabs(ux), limx), v = fmin(fabs(uy), limy);
+  const double jn2 = (k.fx * iz) * (k.fx * iz) * (1.0 + u * u) + (k.fy * iz) * (k.fy * iz) * (1.0 + v * v);
+  const double rb = ceil((double)o.sigma * sqrt(jn2 * g.smax2 + (double)o.eps2d)) + 1.0;
+  return !(floor((mx + rb) / o.tile_w) < 0.0 || floor((my + rb) / o.tile_h) < 0.0 ||
+           floor((mx - rb) / o.tile_w) > tiles_x - 1 || floor((my - rb) / o.tile_h) > tiles_y - 1);
+}
+
+template <class G>
+__device__ __forceinline__ bool project_view(const G &g, const Cam64 &k, const KOpts &o, int tiles_x,
                                              int tiles_y, Proj &P) {
 #pragma unroll
   for (int r = 0; r < 3; r++)
@@ -141,6 +188,7 @@ __device__ __forceinline__ bool project_view(const Geo &g, const Cam64 &k, const
   P.C = P.a * idet;
   const double hd = 0.5 * (P.a - P.c);
   const double lam = 0.5 * (P.a + P.c) + sqrt(hd * hd + P.b * P.b);
+  P.lam = lam;
   const double rad = ceil((double)o.sigma * sqrt(lam));
   const double lox = floor((P.mx - rad) / o.tile_w), hix = floor((P.mx + rad) / o.tile_w);
   const double loy = floor((P.my - rad) / o.tile_h), hiy = floor((P.my + rad) / o.tile_h);
@@ -167,29 +215,29 @@ constexpr double kY3c = 0.45704579946446572;  // sqrt(21/(2 pi))/4
 constexpr double kY3d = 0.37317633259011540;  // sqrt(7/pi)/4
 constexpr double kY3e = 1.4453057213202769;   // sqrt(105/pi)/4
 
-template <int D>
-__device__ __forceinline__ void sh_eval(double x, double y, double z, double *Y) {
-  Y[0] = kY0;
+template <int D, class T>
+__device__ __forceinline__ void sh_eval(T x, T y, T z, T *Y) {
+  Y[0] = (T)kY0;
   if (D >= 1) {
-    Y[1] = -kY1 * y;
-    Y[2] = kY1 * z;
-    Y[3] = -kY1 * x;
+    Y[1] = -(T)kY1 * y;
+    Y[2] = (T)kY1 * z;
+    Y[3] = -(T)kY1 * x;
   }
   if (D >= 2) {
-    const double xx = x * x, yy = y * y, zz = z * z;
-    Y[4] = kY2a * x * y;
-    Y[5] = -kY2a * y * z;
-    Y[6] = kY2b * (2.0 * zz - xx - yy);
-    Y[7] = -kY2a * x * z;
-    Y[8] = kY2c * (xx - yy);
+    const T xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = (T)kY2a * x * y;
+    Y[5] = -(T)kY2a * y * z;
+    Y[6] = (T)kY2b * ((T)2 * zz - xx - yy);
+    Y[7] = -(T)kY2a * x * z;
+    Y[8] = (T)kY2c * (xx - yy);
     if (D >= 3) {
-      Y[9] = -kY3a * y * (3.0 * xx - yy);
-      Y[10] = kY3b * x * y * z;
-      Y[11] = -kY3c * y * (4.0 * zz - xx - yy);
-      Y[12] = kY3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
-      Y[13] = -kY3c * x * (4.0 * zz - xx - yy);
-      Y[14] = kY3e * z * (xx - yy);
-      Y[15] = -kY3a * x * (xx - 3.0 * yy);
+      Y[9] = -(T)kY3a * y * ((T)3 * xx - yy);
+      Y[10] = (T)kY3b * x * y * z;
+      Y[11] = -(T)kY3c * y * ((T)4 * zz - xx - yy);
+      Y[12] = (T)kY3d * z * ((T)2 * zz - (T)3 * xx - (T)3 * yy);
+      Y[13] = -(T)kY3c * x * ((T)4 * zz - xx - yy);
+      Y[14] = (T)kY3e * z * (xx - yy);
+      Y[15] = -(T)kY3a * x * (xx - (T)3 * yy);
     }
   }
 }
@@ -282,5 +330,39 @@ __device__ __forceinline__ float wave_sum_lane63(float x) {
 }
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// ------------------------------------------------------------ shared helpers
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ const float4 *rec_ptr(const KWs &ws, int64_t r) {
+  return reinterpret_cast<const float4 *>(ws.records) + r * kRecordFloat4;
+}
+
+// Global tile id -> view (linear search over at most 32 views).
+__device__ __forceinline__ int view_of_tile(const ViewInfo *views, int n_views, int64_t t) {
+  int v = 0;
+  while (v + 1 < n_views && views[v + 1].tile_base <= t) v++;
+  return v;
+}
+
+// Workgroups of a grid are dispatched to the 8 XCDs round-robin (block b on
+// XCD b % 8).  Give XCD x the contiguous chunk [x * per, (x + 1) * per) of
+// tiles, so neighbouring tiles, which share Gaussians, hit the same L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t count) {
+  const int64_t per = (count + 7) / 8;
+  return (b % 8) * per + b / 8;
+}
+
+__host__ __device__ __forceinline__ int64_t xcd_grid(int64_t count) { return ((count + 7) / 8) * 8; }
+
+static inline int grid_for(int64_t count, int block = kBlock) {
+  int64_t g = (count + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 1048576) g = 1048576;
+  return (int)g;
+}
+
+static inline int last_err() { return (int)hipGetLastError(); }
 
 }  // namespace gsr

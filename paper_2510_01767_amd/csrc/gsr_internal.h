@@ -61,8 +61,8 @@ struct KGrads {
 // Record of one (view, Gaussian) pair, 64 bytes (4 x float4):
 //   r0 = mean2d as float pairs (hi x, hi y, lo x, lo y): mean = hi + lo
 //   r1 = conic (A, B, C), opacity
-//   r2 = colour (r, g, b), depth (camera z)
-//   r3 = rect (x0 | y0 << 16, x1 | y1 << 16), tiles touched, unused
+//   r2 = colour (r, g, b), reach of the alpha >= alpha_min ellipse in pixels
+//   r3 = rect (x0 | y0 << 16, x1 | y1 << 16), depth (camera z, float bits), unused
 constexpr int kRecordFloat4 = 4;
 // 2D gradient of one record: dmean (2), dconic (3), dopacity, dcolour (3), padded to 12 floats.
 constexpr int kGrad2dStride = 12;
@@ -113,5 +113,6 @@ int launch_visibility(const KParams &p, const gsr_camera *cams, const KOpts &o, 
                       const float *aabb6, uint32_t *bits, uint8_t *keep_out, uint8_t *in_block,
                       void *stream);
 int launch_copy_pixels(const KWs &ws, float *T_out, uint32_t *last_out, void *stream);
+int launch_count_visible(const KWs &ws, int64_t n, int n_views, void *stream);
 
 }  // namespace gsr

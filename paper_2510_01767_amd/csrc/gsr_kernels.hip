@@ -9,10 +9,7 @@
 //                per covered tile, scattered into its tile's bucket
 //   sort         per tile, order the bucket by key in LDS (bitonic; merge passes for
 //                buckets larger than one LDS load)
-//   raster       per tile, front-to-back compositing (Sec. 3.2 blending sum)
-//   l1 / bwd     L1 gradient, back-to-front reverse compositing with wave-level
-//                reductions and one atomic per (tile, record, component)
-//   fused        persistent kernel: forward + L1 + reverse per tile, work queue
+//   raster, l1, raster_bwd, fused   (gsr_raster.hip)
 //   project_bwd  per Gaussian, all views: chain rule to the raw parameters and the
 //                densification statistics (Sec. 3.3)
 //
@@ -24,29 +21,6 @@
 
 namespace gsr {
 
-constexpr int kBlock = 256;
-
-__device__ __forceinline__ const float4 *rec_ptr(const KWs &ws, int64_t r) {
-  return reinterpret_cast<const float4 *>(ws.records) + r * kRecordFloat4;
-}
-
-// Global tile id -> view (linear search over at most 32 views).
-__device__ __forceinline__ int view_of_tile(const ViewInfo *views, int n_views, int64_t t) {
-  int v = 0;
-  while (v + 1 < n_views && views[v + 1].tile_base <= t) v++;
-  return v;
-}
-
-// Spread consecutive tiles of a grid over one XCD: blocks are dispatched to
-// the 8 XCDs round-robin, so block b runs on XCD b % 8; give that XCD the
-// contiguous chunk [xcd * per, (xcd + 1) * per) so neighbouring tiles (which
-// share Gaussians) hit the same L2.
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t count) {
-  const int64_t per = (count + 7) / 8;
-  return (b % 8) * per + b / 8;
-}
-
-__host__ __device__ __forceinline__ int64_t xcd_grid(int64_t count) { return ((count + 7) / 8) * 8; }
 
 // ------------------------------------------------------------------ set-up
 
@@ -114,50 +88,49 @@ __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera 
     atomicOr(&ws.hdr->nonfinite, 1u);
     keep = false;
   }
-  Geo g;
-  if (keep) load_geo(p, i, g);
+  GeoF g;
+  if (keep) load_geo_fwd(p, i, g);
   uint32_t bits = (valid && or_bits) ? ws.view_bits[i] : 0u;
-  bool sh_loaded = false;
-  float sh[3 * K];
-  double cc_dir[3];
   for (int v = view_lo; v < view_hi; v++) {
     const ViewInfo &vi = s_view[v];
     const Cam64 cam = cam64(s_cam[v], vi.W, vi.H);
     Proj P;
-    const bool vis = keep && project_view(g, cam, o, vi.tiles_x, vi.tiles_y, P);
-    const uint64_t bal = __ballot(vis);
-    if (lane_id() == 0 && bal) atomicAdd(&ws.hdr->visible[v], (uint32_t)__popcll(bal));
+    // the exact projection only where the conservative bound leaves a chance
+    const bool vis = keep && maybe_visible(g, cam, o, vi.tiles_x, vi.tiles_y) &&
+                     project_view(g, cam, o, vi.tiles_x, vi.tiles_y, P);
     if (!vis) continue;
     bits |= 1u << v;
-    if (!sh_loaded) {
-#pragma unroll
-      for (int k = 0; k < 3 * K; k++) sh[k] = p.sh[(int64_t)k * n + i];
-      sh_loaded = true;
-    }
-    // colour: SH in the direction from the camera centre c = -R^T t to the mean
+    // colour: SH (float32) in the direction from the camera centre c = -R^T t to the mean
+    double d[3];
 #pragma unroll
     for (int a = 0; a < 3; a++)
-      cc_dir[a] = g.mu[a] + (cam.R[a] * cam.t[0] + cam.R[3 + a] * cam.t[1] + cam.R[6 + a] * cam.t[2]);
-    const double dn = sqrt(cc_dir[0] * cc_dir[0] + cc_dir[1] * cc_dir[1] + cc_dir[2] * cc_dir[2]);
-    const double x = cc_dir[0] / dn, y = cc_dir[1] / dn, z = cc_dir[2] / dn;
-    double Y[K];
-    sh_eval<D>(x, y, z, Y);
+      d[a] = g.mu[a] + (cam.R[a] * cam.t[0] + cam.R[3 + a] * cam.t[1] + cam.R[6 + a] * cam.t[2]);
+    const double idn = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    float Y[K];
+    sh_eval<D, float>((float)(d[0] * idn), (float)(d[1] * idn), (float)(d[2] * idn), Y);
     float col[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ch++) {
-      double acc = 0.5;
+      float acc = 0.5f;
 #pragma unroll
-      for (int k = 0; k < K; k++) acc += (double)sh[k * 3 + ch] * Y[k];
-      col[ch] = acc > 0.0 ? (float)acc : 0.0f;
+      for (int k = 0; k < K; k++) acc = __fmaf_rn(p.sh[(int64_t)(k * 3 + ch) * n + i], Y[k], acc);
+      col[ch] = acc > 0.0f ? acc : 0.0f;
     }
     const int64_t r = (int64_t)v * n + i;
     float4 *rec = reinterpret_cast<float4 *>(ws.records) + r * kRecordFloat4;
     const float mxh = (float)P.mx, myh = (float)P.my;
     rec[0] = make_float4(mxh, myh, (float)(P.mx - (double)mxh), (float)(P.my - (double)myh));
     rec[1] = make_float4((float)P.A, (float)P.B, (float)P.C, (float)g.opac);
-    rec[2] = make_float4(col[0], col[1], col[2], (float)P.tc[2]);
-    const uint32_t ntiles = (uint32_t)((P.x1 - P.x0 + 1) * (P.y1 - P.y0 + 1));
-    uint4 r3 = make_uint4((uint32_t)P.x0 | ((uint32_t)P.y0 << 16), (uint32_t)P.x1 | ((uint32_t)P.y1 << 16), ntiles, 0u);
+    // reach of the alpha >= alpha_min ellipse {d : d^T Q d <= 2 ln(o / alpha_min)}:
+    // sqrt(2 ln(o / alpha_min) lambda_max).  The exponent gets 1e-5 of slack
+    // (the float32 exponent and opacity are accurate to ~1e-6) and the reach
+    // a relative and an absolute pad, so no pixel that the float32 alpha test
+    // accepts lies outside it; -1 when even the centre cannot reach alpha_min.
+    const double c2 = 2.0 * log(g.opac / (double)o.alpha_min) + 1e-5;
+    const float reach = c2 > 0.0 ? (float)(sqrt(c2 * P.lam) * 1.001 + 0.01) : -1.0f;
+    rec[2] = make_float4(col[0], col[1], col[2], reach);
+    uint4 r3 = make_uint4((uint32_t)P.x0 | ((uint32_t)P.y0 << 16), (uint32_t)P.x1 | ((uint32_t)P.y1 << 16),
+                          __float_as_uint((float)P.tc[2]), 0u);
     reinterpret_cast<uint4 *>(rec)[3] = r3;
     float4 *g2 = reinterpret_cast<float4 *>(ws.grad2d + r * kGrad2dStride);
     g2[0] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -168,8 +141,38 @@ __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera 
         atomicAdd(&ws.tile_count[vi.tile_base + (int64_t)ty * vi.tiles_x + tx], 1u);
   }
   if (valid) ws.view_bits[i] = bits;
-  const uint64_t anyv = __ballot(valid && bits != 0 && view_hi == p.n_views);
-  if (lane_id() == 0 && anyv) atomicAdd(&ws.hdr->union_count, (uint32_t)__popcll(anyv));
+}
+
+// Per-view visible counts and the union, from view_bits (run on demand by the
+// count query, never inside a step: per-view counters are single addresses
+// that every workgroup would hit).  LDS counters per block, then one device
+// atomic per block and view.
+__global__ __launch_bounds__(kBlock) void k_count_visible(KWs ws, int64_t n, int n_views) {
+  __shared__ uint32_t s_cnt[GSR_MAX_VIEWS + 1];
+  if (threadIdx.x <= GSR_MAX_VIEWS) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t bits = i < n ? ws.view_bits[i] : 0u;
+  for (int v = 0; v < n_views; v++) {
+    const uint64_t m = __ballot((bits >> v) & 1u);
+    if (lane_id() == 0 && m) atomicAdd(&s_cnt[v], (uint32_t)__popcll(m));
+  }
+  const uint64_t u = __ballot(bits != 0u);
+  if (lane_id() == 0 && u) atomicAdd(&s_cnt[GSR_MAX_VIEWS], (uint32_t)__popcll(u));
+  __syncthreads();
+  if ((int)threadIdx.x < n_views && s_cnt[threadIdx.x]) atomicAdd(&ws.hdr->visible[threadIdx.x], s_cnt[threadIdx.x]);
+  if (threadIdx.x == GSR_MAX_VIEWS && s_cnt[GSR_MAX_VIEWS]) atomicAdd(&ws.hdr->union_count, s_cnt[GSR_MAX_VIEWS]);
+}
+
+__global__ void k_zero_visible(KWs ws) {
+  if (threadIdx.x < GSR_MAX_VIEWS) ws.hdr->visible[threadIdx.x] = 0;
+  if (threadIdx.x == 0) ws.hdr->union_count = 0;
+}
+
+int launch_count_visible(const KWs &ws, int64_t n, int n_views, void *stream) {
+  hipLaunchKernelGGL(k_zero_visible, dim3(1), dim3(64), 0, (hipStream_t)stream, ws);
+  hipLaunchKernelGGL(k_count_visible, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, ws, n, n_views);
+  return last_err();
 }
 
 // --------------------------------------------------------------------- scan
@@ -179,43 +182,73 @@ __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera 
 
 constexpr int kScanThreads = 1024;
 
+// Inclusive sum over the 64 lanes of a wavefront (Hillis-Steele with shuffles).
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t y = __shfl_up(x, (unsigned)off);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// Chunks of 4 * 1024 consecutive counts: each thread scans 4 in registers,
+// wavefronts scan thread sums with shuffles, the 16 wavefront sums are
+// scanned by wavefront 0, and a carry walks from chunk to chunk.  View start
+// offsets are recorded on the way (unclamped), giving per-view counts.
 __global__ __launch_bounds__(kScanThreads) void k_scan(KWs ws, int64_t lo, int64_t hi, int64_t base,
                                                         int view_lo, int view_hi) {
-  __shared__ uint64_t s_sum[kScanThreads];
-  const int tid = threadIdx.x;
-  const int64_t len = hi - lo;
-  const int64_t chunk = (len + kScanThreads - 1) / kScanThreads;
-  const int64_t a = lo + tid * chunk;
-  const int64_t b = min(hi, a + chunk);
-  uint64_t s = 0;
-  for (int64_t t = a; t < b; t++) s += ws.tile_count[t];
-  s_sum[tid] = s;
+  constexpr int kWaves = kScanThreads / 64;
+  __shared__ uint64_t s_wave[kWaves];
+  __shared__ uint64_t s_carry;
+  __shared__ uint64_t s_vstart[GSR_MAX_VIEWS + 1];
+  __shared__ int64_t s_vbase[GSR_MAX_VIEWS];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const int nv = view_hi - view_lo;
+  if (tid < nv) s_vbase[tid] = ws.views[view_lo + tid].tile_base;
+  if (tid == 0) s_carry = (uint64_t)base;
   __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    uint64_t add = tid >= off ? s_sum[tid - off] : 0;
-    __syncthreads();
-    s_sum[tid] += add;
-    __syncthreads();
-  }
-  uint64_t run = (uint64_t)base + s_sum[tid] - s;
   const uint64_t cap = (uint64_t)ws.capacity;
-  for (int64_t t = a; t < b; t++) {
-    ws.tile_start[t] = (uint32_t)min(run, cap);
-    run += ws.tile_count[t];
+  for (int64_t c0 = lo; c0 < hi; c0 += 4 * kScanThreads) {
+    const int64_t t0 = c0 + 4 * (int64_t)tid;
+    uint32_t x[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) x[q] = t0 + q < hi ? ws.tile_count[t0 + q] : 0u;
+    const uint64_t s = (uint64_t)x[0] + x[1] + x[2] + x[3];
+    const uint64_t incl = wave_incl_scan(s);
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    if (wave == 0) {
+      const uint64_t w = lane < kWaves ? s_wave[lane] : 0ull;
+      const uint64_t wi = wave_incl_scan(w);
+      if (lane < kWaves) s_wave[lane] = wi - w;  // exclusive
+    }
+    __syncthreads();
+    uint64_t pre = s_carry + s_wave[wave] + (incl - s);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int64_t t = t0 + q;
+      if (t < hi) {
+        ws.tile_start[t] = (uint32_t)min(pre, cap);
+        for (int v = 0; v < nv; v++)
+          if (s_vbase[v] == t) s_vstart[v] = pre;
+      }
+      pre += x[q];
+    }
+    __syncthreads();
+    if (tid == kScanThreads - 1) s_carry = pre;
+    __syncthreads();
   }
-  const uint64_t total = s_sum[kScanThreads - 1];
+  const uint64_t total = s_carry;  // base + all counts
   if (tid == 0) {
-    ws.tile_start[hi] = (uint32_t)min((uint64_t)base + total, cap);
-    if ((uint64_t)base + total > cap) ws.hdr->overflow = 1u;
-    ws.hdr->isect_total = (uint32_t)min((uint64_t)base + total, (uint64_t)0xffffffffu);
+    ws.tile_start[hi] = (uint32_t)min(total, cap);
+    if (total > cap) ws.hdr->overflow = 1u;
+    ws.hdr->isect_total = (uint32_t)min(total, (uint64_t)0xffffffffu);
   }
-  __syncthreads();
-  for (int v = view_lo + tid; v < view_hi; v += kScanThreads) {
-    const ViewInfo vi = ws.views[v];
-    uint64_t sv = 0;
-    // per-view count from the counts themselves (the clamped starts could hide it)
-    for (int64_t t = vi.tile_base; t < vi.tile_base + (int64_t)vi.tiles_x * vi.tiles_y; t++) sv += ws.tile_count[t];
-    ws.hdr->isect[v] = (uint32_t)min(sv, (uint64_t)0xffffffffu);
+  if (tid < nv) {
+    const uint64_t a = s_vstart[tid], b = tid + 1 < nv ? s_vstart[tid + 1] : total;
+    ws.hdr->isect[view_lo + tid] = (uint32_t)min(b - a, (uint64_t)0xffffffffu);
   }
 }
 
@@ -232,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(KWs ws, int64_t n, int n_views,
     const int64_t r = (int64_t)v * n + i;
     const float4 *rec = rec_ptr(ws, r);
     const uint4 r3 = reinterpret_cast<const uint4 *>(rec)[3];
-    const float depth = rec[2].w;
+    const float depth = __uint_as_float(r3.z);
     const ViewInfo vi = ws.views[v];
     const int x0 = r3.x & 0xffff, y0 = r3.x >> 16, x1 = r3.y & 0xffff, y1 = r3.y >> 16;
     const uint64_t key = ((uint64_t)__float_as_uint(depth) << 32) | (uint64_t)(uint32_t)r;
@@ -323,311 +356,6 @@ __global__ __launch_bounds__(kBlock) void k_sort(KWs ws, int64_t tile_lo, int64_
   }
   if (src != keys) {
     for (int64_t k = threadIdx.x; k < n; k += blockDim.x) keys[k] = src[k];
-  }
-}
-
-// ------------------------------------------------------------------ raster
-// Per-tile state and the two tile passes shared by the plain kernels and the
-// fused persistent kernel.  One thread per pixel, 256 pixels per tile.
-
-struct TileCtx {
-  int64_t t;        // global tile id
-  int v;            // view
-  ViewInfo vi;
-  int px, py;       // this thread's pixel
-  bool inside;
-  int64_t start, end;  // entry range [start, end) in keys
-  int64_t pix;      // pixel index within the view
-};
-
-template <int TW, int TH>
-__device__ __forceinline__ void tile_ctx(const KWs &ws, const ViewInfo *views, int n_views, int64_t t, TileCtx &c) {
-  c.t = t;
-  c.v = view_of_tile(views, n_views, t);
-  c.vi = views[c.v];
-  const int64_t local = t - c.vi.tile_base;
-  const int tx = (int)(local % c.vi.tiles_x), ty = (int)(local / c.vi.tiles_x);
-  c.px = tx * TW + (int)(threadIdx.x % TW);
-  c.py = ty * TH + (int)(threadIdx.x / TW);
-  c.inside = c.px < c.vi.W && c.py < c.vi.H;
-  c.pix = (int64_t)c.py * c.vi.W + c.px;
-  c.start = ws.tile_start[t];
-  c.end = min((int64_t)ws.tile_start[t + 1], ws.capacity);
-  if (c.end < c.start) c.end = c.start;
-}
-
-struct LdsRec {
-  float4 r0, r1, r2;
-};
-
-// Front-to-back compositing of one tile.  Returns the colour, the final
-// transmittance and `last` (entries processed before the stop, or the list
-// length).  With hist != nullptr it stores, for every processed entry, the
-// transmittance in front of it (0 when the entry was skipped).
-template <int B>
-__device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsRec *s_rec,
-                                             float C[3], float &T, int &last, float *hist) {
-  const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
-  T = 1.0f;
-  C[0] = C[1] = C[2] = 0.0f;
-  bool done = !c.inside;
-  last = 0;
-  bool stopped = false;
-  for (int64_t b = c.start; b < c.end; b += B) {
-    if (__syncthreads_and(done)) break;
-    if (threadIdx.x < B && b + threadIdx.x < c.end) {
-      const uint32_t r = (uint32_t)ws.keys[b + threadIdx.x];
-      const float4 *rec = rec_ptr(ws, r);
-      s_rec[threadIdx.x].r0 = rec[0];
-      s_rec[threadIdx.x].r1 = rec[1];
-      s_rec[threadIdx.x].r2 = rec[2];
-    }
-    __syncthreads();
-    const int nb = (int)min((int64_t)B, c.end - b);
-    for (int j = 0; j < nb && !done; j++) {
-      const LdsRec &R = s_rec[j];
-      const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, o.alpha_max);
-      float Tin = 0.0f;
-      if (a.alpha >= o.alpha_min) {
-        const float Tn = T * (1.0f - a.alpha);
-        if (Tn < o.T_min) {
-          done = true;
-          stopped = true;
-          last = (int)(b + j - c.start);
-          break;
-        }
-        const float w = a.alpha * T;
-        C[0] = __fmaf_rn(w, R.r2.x, C[0]);
-        C[1] = __fmaf_rn(w, R.r2.y, C[1]);
-        C[2] = __fmaf_rn(w, R.r2.z, C[2]);
-        Tin = T;
-        T = Tn;
-      }
-      if (hist) hist[(b + j) * 256 + threadIdx.x] = Tin;
-    }
-  }
-  if (!stopped) last = c.inside ? (int)(c.end - c.start) : 0;
-}
-
-// Back-to-front reverse pass of one tile for one pixel state.  g: dL/dC_out.
-// T: final transmittance (recompute) - updated in place.  Writes one atomic
-// per non-zero (record, component) of the tile.
-template <int B>
-__device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsRec *s_rec,
-                                              uint32_t *s_idx, float (*s_part)[B][9], int *s_max, float T,
-                                              int last, const float g[3], const float *hist) {
-  const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
-  const int wave = threadIdx.x >> 6;
-  float S[3] = {T * o.bg[0], T * o.bg[1], T * o.bg[2]};
-  const bool active = c.inside && (g[0] != 0.0f || g[1] != 0.0f || g[2] != 0.0f);
-  if (threadIdx.x == 0) *s_max = 0;
-  __syncthreads();
-  if (active && last > 0) atomicMax(s_max, last);
-  __syncthreads();
-  const int64_t hi0 = c.start + *s_max;
-  for (int64_t hi = hi0; hi > c.start; hi -= B) {
-    const int64_t lo = max(c.start, hi - B);
-    const int nb = (int)(hi - lo);
-    __syncthreads();
-    if (threadIdx.x < nb) {
-      const uint32_t r = (uint32_t)ws.keys[lo + threadIdx.x];
-      const float4 *rec = rec_ptr(ws, r);
-      s_rec[threadIdx.x].r0 = rec[0];
-      s_rec[threadIdx.x].r1 = rec[1];
-      s_rec[threadIdx.x].r2 = rec[2];
-      s_idx[threadIdx.x] = r;
-    }
-    __syncthreads();
-    for (int jj = nb - 1; jj >= 0; jj--) {
-      const int64_t j = lo + jj;
-      float v[9];
-#pragma unroll
-      for (int k = 0; k < 9; k++) v[k] = 0.0f;
-      bool contrib = false;
-      if (active && (int)(j - c.start) < last) {
-        const LdsRec &R = s_rec[jj];
-        const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, o.alpha_max);
-        if (a.alpha >= o.alpha_min) {
-          const float om = 1.0f - a.alpha;
-          const float Ti = hist ? hist[j * 256 + threadIdx.x] : T / om;
-          const float wgt = a.alpha * Ti;
-          const float col[3] = {R.r2.x, R.r2.y, R.r2.z};
-          float dLda = 0.0f;
-#pragma unroll
-          for (int ch = 0; ch < 3; ch++) {
-            dLda += g[ch] * (Ti * col[ch] - S[ch] / om);
-            v[6 + ch] = g[ch] * wgt;
-            S[ch] = __fmaf_rn(wgt, col[ch], S[ch]);
-          }
-          if (a.raw < o.alpha_max) {
-            const float gp = dLda * a.alpha;  // dL/dp
-            v[5] = dLda * a.G;
-            v[0] = gp * __fmaf_rn(R.r1.x, a.dx, R.r1.y * a.dy);
-            v[1] = gp * __fmaf_rn(R.r1.y, a.dx, R.r1.z * a.dy);
-            v[2] = -0.5f * gp * a.dx * a.dx;
-            v[3] = -gp * a.dx * a.dy;
-            v[4] = -0.5f * gp * a.dy * a.dy;
-          }
-          contrib = true;
-          T = Ti;
-        }
-      }
-      if (__ballot(contrib) != 0ull) {
-#pragma unroll
-        for (int k = 0; k < 9; k++) v[k] = wave_sum_lane63(v[k]);
-        if (lane_id() == 63)
-#pragma unroll
-          for (int k = 0; k < 9; k++) s_part[wave][jj][k] = v[k];
-      } else if (lane_id() == 63) {
-#pragma unroll
-        for (int k = 0; k < 9; k++) s_part[wave][jj][k] = 0.0f;
-      }
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < nb * 9; idx += blockDim.x) {
-      const int e = idx / 9, k = idx - e * 9;
-      const float sum = s_part[0][e][k] + s_part[1][e][k] + s_part[2][e][k] + s_part[3][e][k];
-      if (sum != 0.0f) unsafeAtomicAdd(&ws.grad2d[(int64_t)s_idx[e] * kGrad2dStride + k], sum);
-    }
-  }
-}
-
-__device__ __forceinline__ float block_sum_fixed(float x, float *s_w) {
-  x = wave_sum_lane63(x);
-  if (lane_id() == 63) s_w[threadIdx.x >> 6] = x;
-  __syncthreads();
-  const float r = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
-  __syncthreads();
-  return r;
-}
-
-template <int TW, int TH, int B>
-__global__ __launch_bounds__(kBlock) void k_raster_fwd(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
-                                                       float *images, int n_views, int store_history) {
-  __shared__ LdsRec s_rec[B];
-  __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
-  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
-  __syncthreads();
-  const int64_t b = xcd_remap(blockIdx.x, tile_count);
-  if (b >= tile_count) return;
-  TileCtx c;
-  tile_ctx<TW, TH>(ws, s_views, n_views, tile_lo + b, c);
-  float C[3], T;
-  int last;
-  tile_forward<B>(ws, o, c, s_rec, C, T, last, store_history ? ws.history : nullptr);
-  if (c.inside) {
-    const int64_t P = (int64_t)c.vi.W * c.vi.H;
-    float *img = images + c.vi.pix_base * 3;
-#pragma unroll
-    for (int ch = 0; ch < 3; ch++) img[ch * P + c.pix] = __fmaf_rn(T, o.bg[ch], C[ch]);
-    ws.pix_T[c.vi.pix_base + c.pix] = T;
-    ws.pix_last[c.vi.pix_base + c.pix] = (uint32_t)last;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_l1(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
-                                               const float *images, const float *targets, int n_views, int tw,
-                                               int th) {
-  __shared__ float s_w[4];
-  __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
-  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
-  __syncthreads();
-  const int64_t t = tile_lo + blockIdx.x;
-  const int v = view_of_tile(s_views, n_views, t);
-  const ViewInfo vi = s_views[v];
-  const int64_t local = t - vi.tile_base;
-  const int px = (int)(local % vi.tiles_x) * tw + (int)(threadIdx.x % tw);
-  const int py = (int)(local / vi.tiles_x) * th + (int)(threadIdx.x / tw);
-  float acc = 0.0f;
-  if (px < vi.W && py < vi.H) {
-    const int64_t P = (int64_t)vi.W * vi.H;
-    const int64_t base = vi.pix_base * 3 + (int64_t)py * vi.W + px;
-#pragma unroll
-    for (int ch = 0; ch < 3; ch++) {
-      const float d = images[base + ch * P] - targets[base + ch * P];
-      acc += fabsf(d);
-      ws.pix_dLdC[base + ch * P] = d > 0.0f ? vi.loss_scale : (d < 0.0f ? -vi.loss_scale : 0.0f);
-    }
-  }
-  const float s = block_sum_fixed(acc, s_w);
-  if (threadIdx.x == 0) ws.tile_loss[t] = s;
-}
-
-template <int TW, int TH, int B>
-__global__ __launch_bounds__(kBlock) void k_raster_bwd(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
-                                                       const float *dLdC, int n_views, int use_history) {
-  __shared__ LdsRec s_rec[B];
-  __shared__ uint32_t s_idx[B];
-  __shared__ float s_part[4][B][9];
-  __shared__ int s_max;
-  __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
-  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
-  __syncthreads();
-  const int64_t b = xcd_remap(blockIdx.x, tile_count);
-  if (b >= tile_count) return;
-  TileCtx c;
-  tile_ctx<TW, TH>(ws, s_views, n_views, tile_lo + b, c);
-  float g[3] = {0.f, 0.f, 0.f};
-  float T = 1.0f;
-  int last = 0;
-  if (c.inside) {
-    const int64_t P = (int64_t)c.vi.W * c.vi.H;
-    const float *d = dLdC + c.vi.pix_base * 3 + c.pix;
-    g[0] = d[0];
-    g[1] = d[P];
-    g[2] = d[2 * P];
-    T = ws.pix_T[c.vi.pix_base + c.pix];
-    last = (int)ws.pix_last[c.vi.pix_base + c.pix];
-  }
-  tile_backward<B>(ws, o, c, s_rec, s_idx, s_part, &s_max, T, last, g, use_history ? ws.history : nullptr);
-}
-
-// Persistent fused forward + L1 + reverse pass.  Workgroups take tiles from
-// ws.hdr->queue (in tile_order when given) until the counter passes the last
-// tile; no workgroup ever waits for another.
-template <int TW, int TH, int B>
-__global__ __launch_bounds__(kBlock) void k_fused(KWs ws, KOpts o, const float *targets, float *images,
-                                                  int n_views, int use_history, const uint32_t *order) {
-  __shared__ LdsRec s_rec[B];
-  __shared__ uint32_t s_idx[B];
-  __shared__ float s_part[4][B][9];
-  __shared__ int s_max;
-  __shared__ float s_w[4];
-  __shared__ int64_t s_item;
-  __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
-  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
-  float *hist = use_history ? ws.history : nullptr;
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(&ws.hdr->queue, 1u);
-    __syncthreads();
-    const int64_t item = s_item;
-    if (item >= ws.tiles_total) break;
-    const int64_t t = order ? (int64_t)order[item] : item;
-    TileCtx c;
-    tile_ctx<TW, TH>(ws, s_views, n_views, t, c);
-    float C[3], T;
-    int last;
-    tile_forward<B>(ws, o, c, s_rec, C, T, last, hist);
-    float g[3] = {0.f, 0.f, 0.f};
-    float acc = 0.0f;
-    if (c.inside) {
-      const int64_t P = (int64_t)c.vi.W * c.vi.H;
-      const int64_t base = c.vi.pix_base * 3 + c.pix;
-#pragma unroll
-      for (int ch = 0; ch < 3; ch++) {
-        const float out = __fmaf_rn(T, o.bg[ch], C[ch]);
-        images[base + ch * P] = out;
-        const float d = out - targets[base + ch * P];
-        acc += fabsf(d);
-        g[ch] = d > 0.0f ? c.vi.loss_scale : (d < 0.0f ? -c.vi.loss_scale : 0.0f);
-      }
-      ws.pix_T[c.vi.pix_base + c.pix] = T;
-      ws.pix_last[c.vi.pix_base + c.pix] = (uint32_t)last;
-    }
-    const float s = block_sum_fixed(acc, s_w);
-    if (threadIdx.x == 0) ws.tile_loss[t] = s;
-    tile_backward<B>(ws, o, c, s_rec, s_idx, s_part, &s_max, T, last, g, hist);
   }
 }
 
@@ -895,12 +623,14 @@ __global__ __launch_bounds__(kBlock) void k_visibility(KParams p, const gsr_came
   const bool keep = p.keep == nullptr || p.keep[i] != 0;
   uint32_t bits = 0;
   if (keep) {
-    Geo g;
-    load_geo(p, i, g);
+    GeoF g;
+    load_geo_fwd(p, i, g);
     for (int v = 0; v < p.n_views; v++) {
       const ViewInfo &vi = s_view[v];
+      const Cam64 cam = cam64(s_cam[v], vi.W, vi.H);
       Proj P;
-      if (project_view(g, cam64(s_cam[v], vi.W, vi.H), o, vi.tiles_x, vi.tiles_y, P)) bits |= 1u << v;
+      if (maybe_visible(g, cam, o, vi.tiles_x, vi.tiles_y) && project_view(g, cam, o, vi.tiles_x, vi.tiles_y, P))
+        bits |= 1u << v;
     }
   }
   if (bits_out) bits_out[i] = bits;
@@ -921,14 +651,6 @@ __global__ void k_copy_pixels(KWs ws, float *T_out, uint32_t *last_out) {
 
 // ---------------------------------------------------------------- launchers
 
-static inline int grid_for(int64_t count, int block = kBlock) {
-  int64_t g = (count + block - 1) / block;
-  if (g < 1) g = 1;
-  if (g > 1048576) g = 1048576;
-  return (int)g;
-}
-
-static inline int last_err() { return (int)hipGetLastError(); }
 
 int launch_setup(const ViewTable &table, const KWs &ws, int64_t zlo, int64_t zcount, int zero_bits, int64_t n,
                  void *stream) {
@@ -979,64 +701,6 @@ int launch_sort(const KWs &ws, int64_t tile_lo, int64_t tile_count, void *stream
   hipLaunchKernelGGL(k_sort, dim3((unsigned)xcd_grid(tile_count)), dim3(kBlock), 0, (hipStream_t)stream, ws,
                      tile_lo, tile_count);
   return last_err();
-}
-
-#define GSR_TILE_DISPATCH(TW_, TH_, CALL)                       \
-  if (o.tile_w == TW_ && o.tile_h == TH_) {                     \
-    if (lds_batch == 64) { constexpr int B = 64; CALL(TW_, TH_, B); }          \
-    else if (lds_batch == 128) { constexpr int B = 128; CALL(TW_, TH_, B); }   \
-    else { constexpr int B = 256; CALL(TW_, TH_, B); }                          \
-    return last_err();                                          \
-  }
-
-int launch_raster_fwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, float *images,
-                      int n_views, int store_history, int lds_batch, void *stream) {
-  if (tile_count <= 0) return 0;
-  const dim3 grid((unsigned)xcd_grid(tile_count)), block(kBlock);
-  hipStream_t s = (hipStream_t)stream;
-#define CALL_FWD(a, b_, B) \
-  hipLaunchKernelGGL((k_raster_fwd<a, b_, B>), grid, block, 0, s, ws, o, tile_lo, tile_count, images, n_views, store_history)
-  GSR_TILE_DISPATCH(16, 16, CALL_FWD)
-  GSR_TILE_DISPATCH(32, 8, CALL_FWD)
-  GSR_TILE_DISPATCH(8, 32, CALL_FWD)
-#undef CALL_FWD
-  return (int)hipErrorInvalidValue;
-}
-
-int launch_l1(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *images,
-              const float *targets, int n_views, void *stream) {
-  if (tile_count <= 0) return 0;
-  hipLaunchKernelGGL(k_l1, dim3((unsigned)tile_count), dim3(kBlock), 0, (hipStream_t)stream, ws, o, tile_lo,
-                     tile_count, images, targets, n_views, o.tile_w, o.tile_h);
-  return last_err();
-}
-
-int launch_raster_bwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *dLdC,
-                      int n_views, int use_history, int lds_batch, void *stream) {
-  if (tile_count <= 0) return 0;
-  const dim3 grid((unsigned)xcd_grid(tile_count)), block(kBlock);
-  hipStream_t s = (hipStream_t)stream;
-#define CALL_BWD(a, b_, B) \
-  hipLaunchKernelGGL((k_raster_bwd<a, b_, B>), grid, block, 0, s, ws, o, tile_lo, tile_count, dLdC, n_views, use_history)
-  GSR_TILE_DISPATCH(16, 16, CALL_BWD)
-  GSR_TILE_DISPATCH(32, 8, CALL_BWD)
-  GSR_TILE_DISPATCH(8, 32, CALL_BWD)
-#undef CALL_BWD
-  return (int)hipErrorInvalidValue;
-}
-
-int launch_fused(const KWs &ws, const KOpts &o, const float *targets, float *images, int n_views,
-                 int use_history, int lds_batch, int grid_blocks, void *stream) {
-  const dim3 grid((unsigned)grid_blocks), block(kBlock);
-  hipStream_t s = (hipStream_t)stream;
-  const uint32_t *order = nullptr;
-#define CALL_FUSED(a, b_, B) \
-  hipLaunchKernelGGL((k_fused<a, b_, B>), grid, block, 0, s, ws, o, targets, images, n_views, use_history, order)
-  GSR_TILE_DISPATCH(16, 16, CALL_FUSED)
-  GSR_TILE_DISPATCH(32, 8, CALL_FUSED)
-  GSR_TILE_DISPATCH(8, 32, CALL_FUSED)
-#undef CALL_FUSED
-  return (int)hipErrorInvalidValue;
 }
 
 int launch_project_bwd(const KParams &p, const gsr_camera *cams, const KOpts &o, const KWs &ws, const KGrads &g,

@@ -1,0 +1,433 @@
+// Tile rasterization kernels (gfx950): front-to-back compositing (the
+// blending sum of Sec. 3.2), the L1 image gradient and the back-to-front
+// reverse pass, as plain per-tile kernels and as one persistent fused kernel.
+//
+// Work decomposition.  One workgroup (4 wavefronts, 256 lanes) owns one tile
+// of 256 pixels, one lane per pixel.  The tile's ordered entry list is
+// streamed through LDS in batches of B records.  Each wavefront then culls
+// the batch against its own 64-pixel strip: an entry is kept only if the
+// ellipse on which its alpha reaches alpha_min (its "reach", precomputed per
+// record) can touch a pixel centre of the strip.  Culled entries have
+// alpha < alpha_min at every pixel of the strip, so the result is identical
+// to evaluating them; on city-scale scenes most entries of a tile list miss
+// most strips, which is where the time would otherwise go.
+//
+// Reverse pass.  Per kept entry, the nine 2D partials of the wave's pixels
+// are summed with DPP (no LDS), skipped entirely when no lane contributes
+// (ballot), and lanes 0..8 issue one atomic add each into the record's
+// gradient slot (nine consecutive floats of one cache line).
+#include <hip/hip_runtime.h>
+
+#include "gsr_device.h"
+
+namespace gsr {
+
+struct TileCtx {
+  int64_t t;  // global tile id
+  int v;      // view
+  ViewInfo vi;
+  int px, py;  // this lane's pixel
+  bool inside;
+  int64_t start, end;  // entry range [start, end) in keys
+  int64_t pix;         // pixel index within the view
+  float wx0, wx1, wy0, wy1;  // pixel-centre box of this lane's wavefront
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ void tile_ctx(const KWs &ws, const ViewInfo *views, int n_views, int64_t t,
+                                         TileCtx &c) {
+  static_assert(TW * TH == kBlock && 64 % TW == 0, "tile must be 256 pixels, whole rows per wavefront");
+  constexpr int kRows = 64 / TW;
+  c.t = t;
+  c.v = view_of_tile(views, n_views, t);
+  c.vi = views[c.v];
+  const int64_t local = t - c.vi.tile_base;
+  const int tx0 = (int)(local % c.vi.tiles_x) * TW, ty0 = (int)(local / c.vi.tiles_x) * TH;
+  c.px = tx0 + (int)(threadIdx.x % TW);
+  c.py = ty0 + (int)(threadIdx.x / TW);
+  c.inside = c.px < c.vi.W && c.py < c.vi.H;
+  c.pix = (int64_t)c.py * c.vi.W + c.px;
+  c.start = ws.tile_start[t];
+  c.end = min((int64_t)ws.tile_start[t + 1], ws.capacity);
+  if (c.end < c.start) c.end = c.start;
+  const int wave = threadIdx.x >> 6;
+  c.wx0 = (float)tx0 + 0.5f;
+  c.wx1 = (float)(tx0 + TW) - 0.5f;
+  c.wy0 = (float)(ty0 + wave * kRows) + 0.5f;
+  c.wy1 = c.wy0 + (float)(kRows - 1);
+}
+
+struct LdsRec {
+  float4 r0, r1, r2;
+};
+
+// Can the entry's alpha reach alpha_min at some pixel centre of this lane's
+// wavefront strip?  (Circle of radius `reach` against the strip's box.)
+__device__ __forceinline__ bool reaches_strip(const LdsRec &R, const TileCtx &c) {
+  const float reach = R.r2.w;
+  if (reach < 0.0f) return false;
+  const float mx = R.r0.x + R.r0.z, my = R.r0.y + R.r0.w;
+  const float ddx = fmaxf(0.0f, fmaxf(c.wx0 - mx, mx - c.wx1));
+  const float ddy = fmaxf(0.0f, fmaxf(c.wy0 - my, my - c.wy1));
+  return ddx * ddx + ddy * ddy <= reach * reach;
+}
+
+__device__ __forceinline__ void load_batch(const KWs &ws, int64_t lo, int nb, LdsRec *s_rec, uint32_t *s_idx) {
+  if ((int)threadIdx.x < nb) {
+    const uint32_t r = (uint32_t)ws.keys[lo + threadIdx.x];
+    const float4 *rec = rec_ptr(ws, r);
+    s_rec[threadIdx.x].r0 = rec[0];
+    s_rec[threadIdx.x].r1 = rec[1];
+    s_rec[threadIdx.x].r2 = rec[2];
+    if (s_idx) s_idx[threadIdx.x] = r;
+  }
+}
+
+// The wavefront's kept entries of the batch, in list order.  Returns the count.
+template <int B>
+__device__ __forceinline__ int strip_list(const LdsRec *s_rec, int nb, const TileCtx &c, uint16_t *list) {
+  const int lane = lane_id();
+  int cnt = 0;
+  for (int jb = 0; jb < nb; jb += 64) {
+    const int j = jb + lane;
+    const bool keep = j < nb && reaches_strip(s_rec[j], c);
+    const uint64_t m = __ballot(keep);
+    if (keep) list[cnt + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)j;
+    cnt += __popcll(m);
+  }
+  return cnt;
+}
+
+// Front-to-back compositing of one tile.  Returns the colour, the final
+// transmittance and `last` (list entries processed before the stop, or the
+// list length).  With hist != nullptr it stores, for every evaluated entry,
+// the transmittance in front of it (0 when the entry was skipped).
+template <int B>
+__device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsRec *s_rec,
+                                             uint16_t (*s_list)[B], float C[3], float &T, int &last,
+                                             float *hist) {
+  const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
+  const int wave = threadIdx.x >> 6;
+  T = 1.0f;
+  C[0] = C[1] = C[2] = 0.0f;
+  bool done = !c.inside;
+  bool stopped = false;
+  last = 0;
+  for (int64_t b = c.start; b < c.end; b += B) {
+    if (__syncthreads_and(done)) break;
+    const int nb = (int)min((int64_t)B, c.end - b);
+    load_batch(ws, b, nb, s_rec, nullptr);
+    __syncthreads();
+    const int cnt = strip_list<B>(s_rec, nb, c, s_list[wave]);
+    __syncthreads();
+    for (int k = 0; k < cnt && !done; k++) {
+      const int j = s_list[wave][k];
+      const LdsRec &R = s_rec[j];
+      const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, o.alpha_max);
+      float Tin = 0.0f;
+      if (a.alpha >= o.alpha_min) {
+        const float Tn = T * (1.0f - a.alpha);
+        if (Tn < o.T_min) {
+          done = true;
+          stopped = true;
+          last = (int)(b + j - c.start);
+          break;
+        }
+        const float w = a.alpha * T;
+        C[0] = __fmaf_rn(w, R.r2.x, C[0]);
+        C[1] = __fmaf_rn(w, R.r2.y, C[1]);
+        C[2] = __fmaf_rn(w, R.r2.z, C[2]);
+        Tin = T;
+        T = Tn;
+      }
+      if (hist) hist[(b + j) * 256 + threadIdx.x] = Tin;
+    }
+  }
+  if (!stopped) last = c.inside ? (int)(c.end - c.start) : 0;
+}
+
+// Back-to-front reverse pass of one tile.  g = dL/dC_out of this lane's
+// pixel, T its final transmittance (recovered entry by entry unless the
+// forward stored it).
+template <int B>
+__device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsRec *s_rec,
+                                              uint32_t *s_idx, uint16_t (*s_list)[B], int *s_max, float T,
+                                              int last, const float g[3], const float *hist) {
+  const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  float S[3] = {T * o.bg[0], T * o.bg[1], T * o.bg[2]};
+  const bool active = c.inside && (g[0] != 0.0f || g[1] != 0.0f || g[2] != 0.0f);
+  __syncthreads();
+  if (threadIdx.x == 0) *s_max = 0;
+  __syncthreads();
+  if (active && last > 0) atomicMax(s_max, last);
+  __syncthreads();
+  const int64_t hi0 = c.start + *s_max;
+  for (int64_t hi = hi0; hi > c.start; hi -= B) {
+    const int64_t lo = max(c.start, hi - B);
+    const int nb = (int)(hi - lo);
+    __syncthreads();
+    load_batch(ws, lo, nb, s_rec, s_idx);
+    __syncthreads();
+    const int cnt = strip_list<B>(s_rec, nb, c, s_list[wave]);
+    __syncthreads();
+    for (int k = cnt - 1; k >= 0; k--) {
+      const int jj = s_list[wave][k];
+      const int64_t j = lo + jj;
+      float v[9];
+#pragma unroll
+      for (int q = 0; q < 9; q++) v[q] = 0.0f;
+      bool contrib = false;
+      if (active && (int)(j - c.start) < last) {
+        const LdsRec &R = s_rec[jj];
+        const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, o.alpha_max);
+        if (a.alpha >= o.alpha_min) {
+          const float om = 1.0f - a.alpha;
+          const float Ti = hist ? hist[j * 256 + threadIdx.x] : T / om;
+          const float wgt = a.alpha * Ti;
+          const float col[3] = {R.r2.x, R.r2.y, R.r2.z};
+          float dLda = 0.0f;
+#pragma unroll
+          for (int ch = 0; ch < 3; ch++) {
+            dLda += g[ch] * (Ti * col[ch] - S[ch] / om);
+            v[6 + ch] = g[ch] * wgt;
+            S[ch] = __fmaf_rn(wgt, col[ch], S[ch]);
+          }
+          if (a.raw < o.alpha_max) {
+            const float gp = dLda * a.alpha;  // dL/dp
+            v[5] = dLda * a.G;
+            v[0] = gp * __fmaf_rn(R.r1.x, a.dx, R.r1.y * a.dy);
+            v[1] = gp * __fmaf_rn(R.r1.y, a.dx, R.r1.z * a.dy);
+            v[2] = -0.5f * gp * a.dx * a.dx;
+            v[3] = -gp * a.dx * a.dy;
+            v[4] = -0.5f * gp * a.dy * a.dy;
+          }
+          contrib = true;
+          T = Ti;
+        }
+      }
+      if (__ballot(contrib) != 0ull) {
+        float mine = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 9; q++) {
+          const float tot = __builtin_bit_cast(float, __builtin_amdgcn_readlane(
+                                                          __builtin_bit_cast(int, wave_sum_lane63(v[q])), 63));
+          mine = lane == q ? tot : mine;
+        }
+        if (lane < 9 && mine != 0.0f)
+          unsafeAtomicAdd(&ws.grad2d[(int64_t)s_idx[jj] * kGrad2dStride + lane], mine);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ float block_sum_fixed(float x, float *s_w) {
+  x = wave_sum_lane63(x);
+  if (lane_id() == 63) s_w[threadIdx.x >> 6] = x;
+  __syncthreads();
+  const float r = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+  __syncthreads();
+  return r;
+}
+
+template <int TW, int TH, int B>
+__global__ __launch_bounds__(kBlock) void k_raster_fwd(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
+                                                       float *images, int n_views, int store_history) {
+  __shared__ LdsRec s_rec[B];
+  __shared__ uint16_t s_list[4][B];
+  __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
+  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
+  __syncthreads();
+  const int64_t b = xcd_remap(blockIdx.x, tile_count);
+  if (b >= tile_count) return;
+  TileCtx c;
+  tile_ctx<TW, TH>(ws, s_views, n_views, tile_lo + b, c);
+  float C[3], T;
+  int last;
+  tile_forward<B>(ws, o, c, s_rec, s_list, C, T, last, store_history ? ws.history : nullptr);
+  if (c.inside) {
+    const int64_t P = (int64_t)c.vi.W * c.vi.H;
+    float *img = images + c.vi.pix_base * 3;
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) img[ch * P + c.pix] = __fmaf_rn(T, o.bg[ch], C[ch]);
+    ws.pix_T[c.vi.pix_base + c.pix] = T;
+    ws.pix_last[c.vi.pix_base + c.pix] = (uint32_t)last;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_l1(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
+                                               const float *images, const float *targets, int n_views, int tw,
+                                               int th) {
+  __shared__ float s_w[4];
+  __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
+  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
+  __syncthreads();
+  const int64_t t = tile_lo + blockIdx.x;
+  const int v = view_of_tile(s_views, n_views, t);
+  const ViewInfo vi = s_views[v];
+  const int64_t local = t - vi.tile_base;
+  const int px = (int)(local % vi.tiles_x) * tw + (int)(threadIdx.x % tw);
+  const int py = (int)(local / vi.tiles_x) * th + (int)(threadIdx.x / tw);
+  float acc = 0.0f;
+  if (px < vi.W && py < vi.H) {
+    const int64_t P = (int64_t)vi.W * vi.H;
+    const int64_t base = vi.pix_base * 3 + (int64_t)py * vi.W + px;
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) {
+      const float d = images[base + ch * P] - targets[base + ch * P];
+      acc += fabsf(d);
+      ws.pix_dLdC[base + ch * P] = d > 0.0f ? vi.loss_scale : (d < 0.0f ? -vi.loss_scale : 0.0f);
+    }
+  }
+  const float s = block_sum_fixed(acc, s_w);
+  if (threadIdx.x == 0) ws.tile_loss[t] = s;
+}
+
+template <int TW, int TH, int B>
+__global__ __launch_bounds__(kBlock) void k_raster_bwd(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
+                                                       const float *dLdC, int n_views, int use_history) {
+  __shared__ LdsRec s_rec[B];
+  __shared__ uint32_t s_idx[B];
+  __shared__ uint16_t s_list[4][B];
+  __shared__ int s_max;
+  __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
+  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
+  __syncthreads();
+  const int64_t b = xcd_remap(blockIdx.x, tile_count);
+  if (b >= tile_count) return;
+  TileCtx c;
+  tile_ctx<TW, TH>(ws, s_views, n_views, tile_lo + b, c);
+  float g[3] = {0.f, 0.f, 0.f};
+  float T = 1.0f;
+  int last = 0;
+  if (c.inside) {
+    const int64_t P = (int64_t)c.vi.W * c.vi.H;
+    const float *d = dLdC + c.vi.pix_base * 3 + c.pix;
+    g[0] = d[0];
+    g[1] = d[P];
+    g[2] = d[2 * P];
+    T = ws.pix_T[c.vi.pix_base + c.pix];
+    last = (int)ws.pix_last[c.vi.pix_base + c.pix];
+  }
+  tile_backward<B>(ws, o, c, s_rec, s_idx, s_list, &s_max, T, last, g, use_history ? ws.history : nullptr);
+}
+
+// Persistent fused forward + L1 + reverse pass.  Workgroups take tiles from
+// ws.hdr->queue (in `order` when given) until the counter passes the last
+// tile; no workgroup ever waits for another.
+template <int TW, int TH, int B>
+__global__ __launch_bounds__(kBlock) void k_fused(KWs ws, KOpts o, const float *targets, float *images,
+                                                  int n_views, int use_history, const uint32_t *order) {
+  __shared__ LdsRec s_rec[B];
+  __shared__ uint32_t s_idx[B];
+  __shared__ uint16_t s_list[4][B];
+  __shared__ int s_max;
+  __shared__ float s_w[4];
+  __shared__ int64_t s_item;
+  __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
+  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
+  float *hist = use_history ? ws.history : nullptr;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(&ws.hdr->queue, 1u);
+    __syncthreads();
+    const int64_t item = s_item;
+    if (item >= ws.tiles_total) break;
+    const int64_t t = order ? (int64_t)order[item] : item;
+    TileCtx c;
+    tile_ctx<TW, TH>(ws, s_views, n_views, t, c);
+    float C[3], T;
+    int last;
+    tile_forward<B>(ws, o, c, s_rec, s_list, C, T, last, hist);
+    float g[3] = {0.f, 0.f, 0.f};
+    float acc = 0.0f;
+    if (c.inside) {
+      const int64_t P = (int64_t)c.vi.W * c.vi.H;
+      const int64_t base = c.vi.pix_base * 3 + c.pix;
+#pragma unroll
+      for (int ch = 0; ch < 3; ch++) {
+        const float out = __fmaf_rn(T, o.bg[ch], C[ch]);
+        images[base + ch * P] = out;
+        const float d = out - targets[base + ch * P];
+        acc += fabsf(d);
+        g[ch] = d > 0.0f ? c.vi.loss_scale : (d < 0.0f ? -c.vi.loss_scale : 0.0f);
+      }
+      ws.pix_T[c.vi.pix_base + c.pix] = T;
+      ws.pix_last[c.vi.pix_base + c.pix] = (uint32_t)last;
+    }
+    const float s = block_sum_fixed(acc, s_w);
+    if (threadIdx.x == 0) ws.tile_loss[t] = s;
+    tile_backward<B>(ws, o, c, s_rec, s_idx, s_list, &s_max, T, last, g, hist);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+#define GSR_TILE_DISPATCH(TW_, TH_, CALL)                                   \
+  if (o.tile_w == TW_ && o.tile_h == TH_) {                                 \
+    if (lds_batch == 64) {                                                  \
+      constexpr int B = 64;                                                 \
+      CALL(TW_, TH_, B);                                                    \
+    } else if (lds_batch == 128) {                                          \
+      constexpr int B = 128;                                                \
+      CALL(TW_, TH_, B);                                                    \
+    } else {                                                                \
+      constexpr int B = 256;                                                \
+      CALL(TW_, TH_, B);                                                    \
+    }                                                                       \
+    return last_err();                                                      \
+  }
+
+int launch_raster_fwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, float *images,
+                      int n_views, int store_history, int lds_batch, void *stream) {
+  if (tile_count <= 0) return 0;
+  const dim3 grid((unsigned)xcd_grid(tile_count)), block(kBlock);
+  hipStream_t s = (hipStream_t)stream;
+#define CALL_FWD(a, b_, B)                                                                                  \
+  hipLaunchKernelGGL((k_raster_fwd<a, b_, B>), grid, block, 0, s, ws, o, tile_lo, tile_count, images, n_views, \
+                     store_history)
+  GSR_TILE_DISPATCH(16, 16, CALL_FWD)
+  GSR_TILE_DISPATCH(32, 8, CALL_FWD)
+  GSR_TILE_DISPATCH(8, 32, CALL_FWD)
+#undef CALL_FWD
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_l1(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *images,
+              const float *targets, int n_views, void *stream) {
+  if (tile_count <= 0) return 0;
+  hipLaunchKernelGGL(k_l1, dim3((unsigned)tile_count), dim3(kBlock), 0, (hipStream_t)stream, ws, o, tile_lo,
+                     tile_count, images, targets, n_views, o.tile_w, o.tile_h);
+  return last_err();
+}
+
+int launch_raster_bwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *dLdC,
+                      int n_views, int use_history, int lds_batch, void *stream) {
+  if (tile_count <= 0) return 0;
+  const dim3 grid((unsigned)xcd_grid(tile_count)), block(kBlock);
+  hipStream_t s = (hipStream_t)stream;
+#define CALL_BWD(a, b_, B)                                                                                 \
+  hipLaunchKernelGGL((k_raster_bwd<a, b_, B>), grid, block, 0, s, ws, o, tile_lo, tile_count, dLdC, n_views, \
+                     use_history)
+  GSR_TILE_DISPATCH(16, 16, CALL_BWD)
+  GSR_TILE_DISPATCH(32, 8, CALL_BWD)
+  GSR_TILE_DISPATCH(8, 32, CALL_BWD)
+#undef CALL_BWD
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_fused(const KWs &ws, const KOpts &o, const float *targets, float *images, int n_views, int use_history,
+                 int lds_batch, int grid_blocks, void *stream) {
+  const dim3 grid((unsigned)grid_blocks), block(kBlock);
+  hipStream_t s = (hipStream_t)stream;
+  const uint32_t *order = nullptr;
+#define CALL_FUSED(a, b_, B) \
+  hipLaunchKernelGGL((k_fused<a, b_, B>), grid, block, 0, s, ws, o, targets, images, n_views, use_history, order)
+  GSR_TILE_DISPATCH(16, 16, CALL_FUSED)
+  GSR_TILE_DISPATCH(32, 8, CALL_FUSED)
+  GSR_TILE_DISPATCH(8, 32, CALL_FUSED)
+#undef CALL_FUSED
+  return (int)hipErrorInvalidValue;
+}
+
+}  // namespace gsr
