@@ -149,7 +149,7 @@ typedef struct gsr_counts {
 /* Internal byte offsets of the workspace (for tests and profiling). */
 typedef struct gsr_layout {
   size_t header, view_table, view_bits, records, grad2d, tile_count, tile_start, tile_fill,
-      tile_loss, tile_order, keys, keys_alt, pix_T, pix_last, pix_dLdC, history, total;
+      tile_loss, tile_order, keys, keys_alt, ranks, pix_T, pix_last, pix_dLdC, history, total;
   int64_t vn;              /* n_views * n record slots (record of (v, i) at v * n + i) */
   int64_t tiles_total;     /* tiles over all views for the plan's tile shape */
   int64_t pixels_total;

@@ -97,6 +97,7 @@ void compute_layout(gsr_plan &p) {
   take(L.tile_order, sizeof(uint32_t) * (size_t)tmax);
   take(L.keys, sizeof(uint64_t) * (size_t)L.capacity);
   take(L.keys_alt, sizeof(uint64_t) * (size_t)L.capacity);
+  take(L.ranks, sizeof(uint32_t) * 4 * (size_t)L.vn);
   take(L.pix_T, sizeof(float) * (size_t)L.pixels_total);
   take(L.pix_last, sizeof(uint32_t) * (size_t)L.pixels_total);
   take(L.pix_dLdC, sizeof(float) * 3 * (size_t)L.pixels_total);
@@ -236,6 +237,7 @@ KWs ws_view(const gsr_plan &p, void *ws) {
   k.tile_order = (uint32_t *)(b + L.tile_order);
   k.keys = (uint64_t *)(b + L.keys);
   k.keys_alt = (uint64_t *)(b + L.keys_alt);
+  k.ranks = (uint32_t *)(b + L.ranks);
   k.pix_T = (float *)(b + L.pix_T);
   k.pix_last = (uint32_t *)(b + L.pix_last);
   k.pix_dLdC = (float *)(b + L.pix_dLdC);
@@ -366,6 +368,7 @@ gsr_status enqueue_batched_l1(gsr_plan *plan, const gsr_gaussians *g, const gsr_
   const KOpts ko = kopts(*plan);
   const int V = plan->prob.n_views;
   const int grid = n_cus(plan) * plan->opt.grid_per_cu;
+  STAGE(launch_tile_order(ws, stream), "order");
   STAGE(launch_fused(ws, ko, targets, images, V, use_history(*plan) ? 1 : 0, plan->opt.lds_batch, grid, stream),
          "fused raster");
   STAGE(launch_project_bwd(kparams(*plan, g), cams, ko, ws, kgrads(grads), stats ? stats->grad2d_norm_sum : nullptr,

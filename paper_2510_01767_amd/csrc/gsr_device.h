@@ -296,15 +296,18 @@ struct PairAlpha {
   float dx, dy, G, raw, alpha;
 };
 
+// pmin is a per-record lower bound on the exponent below which o e^p cannot
+// reach alpha_min (ln(alpha_min / o) minus a slack): such pairs skip the
+// exponential; the alpha test itself still decides every pair.
 __device__ __forceinline__ PairAlpha pair_alpha(float pxc, float pyc, const float4 &r0, const float4 &r1,
-                                                float alpha_max) {
+                                                float pmin, float alpha_max) {
   PairAlpha a;
   a.dx = (pxc - r0.x) - r0.z;
   a.dy = (pyc - r0.y) - r0.w;
   // p = -(A dx^2 + C dy^2) / 2 - B dx dy
   const float quad = __fmaf_rn(r1.x * a.dx, a.dx, r1.z * a.dy * a.dy);
   const float p = __fmaf_rn(-0.5f, quad, -(r1.y * a.dx * a.dy));
-  a.G = p > 0.0f ? -1.0f : expf(p);  // G < 0 marks "skip: p > 0"
+  a.G = (p > 0.0f || p < pmin) ? -1.0f : expf(p);  // G < 0 marks a skipped pair
   a.raw = r1.w * a.G;
   a.alpha = fminf(alpha_max, a.raw);
   return a;

@@ -34,7 +34,12 @@ struct WsHeader {
   uint32_t pad[3];
   uint32_t isect[GSR_MAX_VIEWS];
   uint32_t visible[GSR_MAX_VIEWS];
+  // longest-list-first schedule of the persistent raster: tiles per length
+  // bin (descending) and the bins' fill cursors
+  uint32_t order_bins[1024];
+  uint32_t order_cursor[1024];
 };
+constexpr int kOrderBins = 1024;
 
 // Rasterizer constants as kernel arguments.
 struct KOpts {
@@ -61,8 +66,9 @@ struct KGrads {
 // Record of one (view, Gaussian) pair, 64 bytes (4 x float4):
 //   r0 = mean2d as float pairs (hi x, hi y, lo x, lo y): mean = hi + lo
 //   r1 = conic (A, B, C), opacity
-//   r2 = colour (r, g, b), reach of the alpha >= alpha_min ellipse in pixels
-//   r3 = rect (x0 | y0 << 16, x1 | y1 << 16), depth (camera z, float bits), unused
+//   r2 = colour (r, g, b), pmin (exponent below which alpha < alpha_min)
+//   r3 = rect (x0 | y0 << 16, x1 | y1 << 16), depth (camera z, float bits),
+//        reach of the alpha >= alpha_min ellipse in pixels (float bits)
 constexpr int kRecordFloat4 = 4;
 // 2D gradient of one record: dmean (2), dconic (3), dopacity, dcolour (3), padded to 12 floats.
 constexpr int kGrad2dStride = 12;
@@ -77,6 +83,7 @@ struct KWs {
   float *tile_loss;
   uint32_t *tile_order;
   uint64_t *keys, *keys_alt;
+  uint32_t *ranks;  // [vn][4]: in-tile rank of a record's first four tiles
   float *pix_T;
   uint32_t *pix_last;
   float *pix_dLdC;
@@ -114,5 +121,6 @@ int launch_visibility(const KParams &p, const gsr_camera *cams, const KOpts &o, 
                       void *stream);
 int launch_copy_pixels(const KWs &ws, float *T_out, uint32_t *last_out, void *stream);
 int launch_count_visible(const KWs &ws, int64_t n, int n_views, void *stream);
+int launch_tile_order(const KWs &ws, void *stream);
 
 }  // namespace gsr

@@ -40,6 +40,7 @@ __global__ void k_setup(ViewTable table, KWs ws, int64_t zlo, int64_t zcount, in
     ws.hdr->isect[gid] = 0;
     ws.hdr->visible[gid] = 0;
   }
+  for (int64_t k = gid; k < kOrderBins; k += stride) ws.hdr->order_bins[k] = 0;
   for (int64_t k = gid; k < zcount; k += stride) {
     ws.tile_count[zlo + k] = 0;
     ws.tile_fill[zlo + k] = 0;
@@ -128,17 +129,36 @@ __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera 
     // accepts lies outside it; -1 when even the centre cannot reach alpha_min.
     const double c2 = 2.0 * log(g.opac / (double)o.alpha_min) + 1e-5;
     const float reach = c2 > 0.0 ? (float)(sqrt(c2 * P.lam) * 1.001 + 0.01) : -1.0f;
-    rec[2] = make_float4(col[0], col[1], col[2], reach);
+    // below pmin the float32 exponent cannot give alpha >= alpha_min (same slack)
+    const float pmin = c2 > 0.0 ? (float)(-0.5 * c2) : 0.0f;
+    rec[2] = make_float4(col[0], col[1], col[2], pmin);
     uint4 r3 = make_uint4((uint32_t)P.x0 | ((uint32_t)P.y0 << 16), (uint32_t)P.x1 | ((uint32_t)P.y1 << 16),
-                          __float_as_uint((float)P.tc[2]), 0u);
+                          __float_as_uint((float)P.tc[2]), __float_as_uint(reach));
     reinterpret_cast<uint4 *>(rec)[3] = r3;
     float4 *g2 = reinterpret_cast<float4 *>(ws.grad2d + r * kGrad2dStride);
     g2[0] = make_float4(0.f, 0.f, 0.f, 0.f);
     g2[1] = make_float4(0.f, 0.f, 0.f, 0.f);
     g2[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    // Count the record into each tile it touches.  For the first four tiles
+    // the count atomic's return value is the record's rank in that tile's
+    // bucket, kept so that the scatter needs no atomics; further tiles (large
+    // footprints, rare) are counted apart and placed after the ranked ones.
+    uint4 rk = make_uint4(0u, 0u, 0u, 0u);
+    int k = 0;
     for (int ty = P.y0; ty <= P.y1; ty++)
-      for (int tx = P.x0; tx <= P.x1; tx++)
-        atomicAdd(&ws.tile_count[vi.tile_base + (int64_t)ty * vi.tiles_x + tx], 1u);
+      for (int tx = P.x0; tx <= P.x1; tx++, k++) {
+        const int64_t t = vi.tile_base + (int64_t)ty * vi.tiles_x + tx;
+        if (k < 4) {
+          const uint32_t rank = atomicAdd(&ws.tile_count[t], 1u);
+          rk.x = k == 0 ? rank : rk.x;
+          rk.y = k == 1 ? rank : rk.y;
+          rk.z = k == 2 ? rank : rk.z;
+          rk.w = k == 3 ? rank : rk.w;
+        } else {
+          atomicAdd(&ws.tile_fill[t], 1u);
+        }
+      }
+    reinterpret_cast<uint4 *>(ws.ranks)[r] = rk;
   }
   if (valid) ws.view_bits[i] = bits;
 }
@@ -214,7 +234,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(KWs ws, int64_t lo, int64
     const int64_t t0 = c0 + 4 * (int64_t)tid;
     uint32_t x[4];
 #pragma unroll
-    for (int q = 0; q < 4; q++) x[q] = t0 + q < hi ? ws.tile_count[t0 + q] : 0u;
+    for (int q = 0; q < 4; q++) x[q] = t0 + q < hi ? ws.tile_count[t0 + q] + ws.tile_fill[t0 + q] : 0u;
     const uint64_t s = (uint64_t)x[0] + x[1] + x[2] + x[3];
     const uint64_t incl = wave_incl_scan(s);
     if (lane == 63) s_wave[wave] = incl;
@@ -269,10 +289,16 @@ __global__ __launch_bounds__(kBlock) void k_emit(KWs ws, int64_t n, int n_views,
     const ViewInfo vi = ws.views[v];
     const int x0 = r3.x & 0xffff, y0 = r3.x >> 16, x1 = r3.y & 0xffff, y1 = r3.y >> 16;
     const uint64_t key = ((uint64_t)__float_as_uint(depth) << 32) | (uint64_t)(uint32_t)r;
+    const uint4 rk = reinterpret_cast<const uint4 *>(ws.ranks)[r];
+    int k = 0;
     for (int ty = y0; ty <= y1; ty++)
-      for (int tx = x0; tx <= x1; tx++) {
+      for (int tx = x0; tx <= x1; tx++, k++) {
         const int64_t t = vi.tile_base + (int64_t)ty * vi.tiles_x + tx;
-        const uint64_t slot = (uint64_t)ws.tile_start[t] + atomicAdd(&ws.tile_fill[t], 1u);
+        // ranked entries first, then the overflow entries of large footprints
+        // (tile_fill counted them; counting it back down places them)
+        const uint32_t rank = k == 0 ? rk.x : k == 1 ? rk.y : k == 2 ? rk.z : k == 3 ? rk.w
+                                     : ws.tile_count[t] + atomicSub(&ws.tile_fill[t], 1u) - 1u;
+        const uint64_t slot = (uint64_t)ws.tile_start[t] + rank;
         if (slot < (uint64_t)ws.capacity && slot < (uint64_t)ws.tile_start[t + 1]) ws.keys[slot] = key;
       }
   }

@@ -58,13 +58,14 @@ __device__ __forceinline__ void tile_ctx(const KWs &ws, const ViewInfo *views, i
 }
 
 struct LdsRec {
-  float4 r0, r1, r2;
+  float4 r0, r1, r2;  // mean (hi, lo), conic + opacity, colour + pmin
+  float reach;
 };
 
 // Can the entry's alpha reach alpha_min at some pixel centre of this lane's
 // wavefront strip?  (Circle of radius `reach` against the strip's box.)
 __device__ __forceinline__ bool reaches_strip(const LdsRec &R, const TileCtx &c) {
-  const float reach = R.r2.w;
+  const float reach = R.reach;
   if (reach < 0.0f) return false;
   const float mx = R.r0.x + R.r0.z, my = R.r0.y + R.r0.w;
   const float ddx = fmaxf(0.0f, fmaxf(c.wx0 - mx, mx - c.wx1));
@@ -79,6 +80,7 @@ __device__ __forceinline__ void load_batch(const KWs &ws, int64_t lo, int nb, Ld
     s_rec[threadIdx.x].r0 = rec[0];
     s_rec[threadIdx.x].r1 = rec[1];
     s_rec[threadIdx.x].r2 = rec[2];
+    s_rec[threadIdx.x].reach = __uint_as_float(reinterpret_cast<const uint4 *>(rec)[3].w);
     if (s_idx) s_idx[threadIdx.x] = r;
   }
 }
@@ -123,7 +125,7 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
     for (int k = 0; k < cnt && !done; k++) {
       const int j = s_list[wave][k];
       const LdsRec &R = s_rec[j];
-      const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, o.alpha_max);
+      const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, o.alpha_max);
       float Tin = 0.0f;
       if (a.alpha >= o.alpha_min) {
         const float Tn = T * (1.0f - a.alpha);
@@ -180,16 +182,18 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
       bool contrib = false;
       if (active && (int)(j - c.start) < last) {
         const LdsRec &R = s_rec[jj];
-        const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, o.alpha_max);
+        const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, o.alpha_max);
         if (a.alpha >= o.alpha_min) {
-          const float om = 1.0f - a.alpha;
-          const float Ti = hist ? hist[j * 256 + threadIdx.x] : T / om;
+          // 1 / (1 - alpha) by the hardware reciprocal (1 ulp): T and the
+          // suffix only feed gradients, never a discrete decision
+          const float inv_om = __builtin_amdgcn_rcpf(1.0f - a.alpha);
+          const float Ti = hist ? hist[j * 256 + threadIdx.x] : T * inv_om;
           const float wgt = a.alpha * Ti;
           const float col[3] = {R.r2.x, R.r2.y, R.r2.z};
           float dLda = 0.0f;
 #pragma unroll
           for (int ch = 0; ch < 3; ch++) {
-            dLda += g[ch] * (Ti * col[ch] - S[ch] / om);
+            dLda += g[ch] * (Ti * col[ch] - S[ch] * inv_om);
             v[6 + ch] = g[ch] * wgt;
             S[ch] = __fmaf_rn(wgt, col[ch], S[ch]);
           }
@@ -361,6 +365,61 @@ __global__ __launch_bounds__(kBlock) void k_fused(KWs ws, KOpts o, const float *
   }
 }
 
+// ------------------------------------------------------- longest list first
+// The persistent kernel takes tiles in descending list length (bins of 4
+// entries), so the longest tiles start first and the tail of the launch is
+// made of short ones.  The order only schedules work: every tile's result is
+// the same whichever workgroup computes it, whenever.
+
+__device__ __forceinline__ int order_bin(const KWs &ws, int64_t t) {
+  const uint32_t n = ws.tile_start[t + 1] - ws.tile_start[t];
+  return kOrderBins - 1 - (int)min(n >> 2, (uint32_t)(kOrderBins - 1));
+}
+
+__global__ __launch_bounds__(kBlock) void k_order_hist(KWs ws) {
+  __shared__ uint32_t s_h[kOrderBins];
+  for (int k = threadIdx.x; k < kOrderBins; k += blockDim.x) s_h[k] = 0;
+  __syncthreads();
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ws.tiles_total;
+       t += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&s_h[order_bin(ws, t)], 1u);
+  __syncthreads();
+  for (int k = threadIdx.x; k < kOrderBins; k += blockDim.x)
+    if (s_h[k]) atomicAdd(&ws.hdr->order_bins[k], s_h[k]);
+}
+
+__global__ __launch_bounds__(kOrderBins) void k_order_scan(KWs ws) {
+  __shared__ uint32_t s[kOrderBins];
+  const int k = threadIdx.x;
+  const uint32_t x = ws.hdr->order_bins[k];
+  s[k] = x;
+  __syncthreads();
+  for (int off = 1; off < kOrderBins; off <<= 1) {
+    const uint32_t y = k >= off ? s[k - off] : 0u;
+    __syncthreads();
+    s[k] += y;
+    __syncthreads();
+  }
+  ws.hdr->order_cursor[k] = s[k] - x;
+}
+
+__global__ __launch_bounds__(kBlock) void k_order_scatter(KWs ws) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ws.tiles_total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t pos = atomicAdd(&ws.hdr->order_cursor[order_bin(ws, t)], 1u);
+    ws.tile_order[pos] = (uint32_t)t;
+  }
+}
+
+int launch_tile_order(const KWs &ws, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const int g = (int)min((int64_t)256, (ws.tiles_total + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_order_hist, dim3(g), dim3(kBlock), 0, s, ws);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderBins), 0, s, ws);
+  hipLaunchKernelGGL(k_order_scatter, dim3(grid_for(ws.tiles_total)), dim3(kBlock), 0, s, ws);
+  return last_err();
+}
+
 // ---------------------------------------------------------------- launchers
 
 #define GSR_TILE_DISPATCH(TW_, TH_, CALL)                                   \
@@ -420,7 +479,7 @@ int launch_fused(const KWs &ws, const KOpts &o, const float *targets, float *ima
                  int lds_batch, int grid_blocks, void *stream) {
   const dim3 grid((unsigned)grid_blocks), block(kBlock);
   hipStream_t s = (hipStream_t)stream;
-  const uint32_t *order = nullptr;
+  const uint32_t *order = ws.tile_order;
 #define CALL_FUSED(a, b_, B) \
   hipLaunchKernelGGL((k_fused<a, b_, B>), grid, block, 0, s, ws, o, targets, images, n_views, use_history, order)
   GSR_TILE_DISPATCH(16, 16, CALL_FUSED)

@@ -74,7 +74,7 @@ class gsr_counts(ctypes.Structure):
 
 class gsr_layout(ctypes.Structure):
     _fields_ = [(k, _sz) for k in ("header", "view_table", "view_bits", "records", "grad2d", "tile_count",
-                                   "tile_start", "tile_fill", "tile_loss", "tile_order", "keys", "keys_alt",
+                                   "tile_start", "tile_fill", "tile_loss", "tile_order", "keys", "keys_alt", "ranks",
                                    "pix_T", "pix_last", "pix_dLdC", "history", "total")] + \
                [(k, _i64) for k in ("vn", "tiles_total", "pixels_total", "capacity", "history_entries")]
 

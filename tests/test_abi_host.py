@@ -97,7 +97,7 @@ def test_layout_and_workspace_size():
     size = C.gsr_workspace_size(plan)
     assert size == L.total
     fields = ["header", "view_table", "view_bits", "records", "grad2d", "tile_count", "tile_start",
-              "tile_fill", "tile_loss", "tile_order", "keys", "keys_alt", "pix_T", "pix_last", "pix_dLdC",
+              "tile_fill", "tile_loss", "tile_order", "keys", "keys_alt", "ranks", "pix_T", "pix_last", "pix_dLdC",
               "history"]
     offs = [getattr(L, f) for f in fields]
     assert all(x % 256 == 0 for x in offs)

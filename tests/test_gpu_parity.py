@@ -111,7 +111,10 @@ def test_records_and_binning_bit_exact(scene_name, c0, ragged):
         np.testing.assert_allclose(rv[:, 14], o["depth"][sel], rtol=3e-7)
         # the per-record reach bounds every pixel centre where the oracle's
         # alpha clears alpha_min (used to cull entries per wavefront)
-        reach = rv[:, 11].astype(np.float64)
+        reach = rv[:, 15].astype(np.float64)
+        # pmin lower-bounds the exponent of every pair the alpha test accepts
+        pmin = rv[:, 11].astype(np.float64)
+        np.testing.assert_array_less(pmin, np.log(parity.opts_for().alpha_min / o["opacity"][sel]) + 1e-12)
         idx = np.nonzero(sel)[0]
         W, H = scene.cameras[v]["W"], scene.cameras[v]["H"]
         ys, xs = np.mgrid[0:H, 0:W]
