@@ -92,7 +92,10 @@ typedef struct gsr_options {
   int32_t accumulate_grads; /* 0: gradients are overwritten; 1: added to */
   int32_t check_finite;  /* 1: flag non-finite parameters (GSR_ERR_NONFINITE via query) */
   int32_t profile_stages; /* 1: time every stage of eager calls with device events */
-  int32_t reserved;
+  int32_t bwd_reduce;     /* reverse-pass reduction: 0 = wavefront DPP sums + one device atomic per
+                             (wavefront, record, component); 1 = per-lane LDS float atomics into a
+                             per-batch accumulator + one device atomic per (tile, record,
+                             component); 2 = as 1 after DPP sums over lane quads */
   float near_plane, far_plane;
   float eps2d;           /* low-pass dilation of the 2D covariance */
   float sigma_extent;    /* footprint radius in standard deviations */

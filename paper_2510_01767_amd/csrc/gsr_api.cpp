@@ -113,6 +113,7 @@ gsr_status validate_options(const gsr_options &o) {
   if (o.bwd_variant < GSR_BWD_AUTO || o.bwd_variant > GSR_BWD_STORED) return GSR_ERR_INVALID_ARG;
   if (o.lds_batch != 64 && o.lds_batch != 128 && o.lds_batch != 256) return GSR_ERR_INVALID_ARG;
   if (o.grid_per_cu < 1 || o.grid_per_cu > 32) return GSR_ERR_INVALID_ARG;
+  if (o.bwd_reduce < 0 || o.bwd_reduce > 2) return GSR_ERR_INVALID_ARG;
   if (!(o.near_plane > 0.0f) || !(o.far_plane > o.near_plane)) return GSR_ERR_INVALID_ARG;
   if (!(o.eps2d >= 0.0f) || !(o.sigma_extent > 0.0f) || !(o.jac_clamp > 0.0f)) return GSR_ERR_INVALID_ARG;
   if (!(o.alpha_min > 0.0f) || !(o.alpha_max > o.alpha_min) || !(o.alpha_max < 1.0f)) return GSR_ERR_INVALID_ARG;
@@ -369,7 +370,8 @@ gsr_status enqueue_batched_l1(gsr_plan *plan, const gsr_gaussians *g, const gsr_
   const int V = plan->prob.n_views;
   const int grid = n_cus(plan) * plan->opt.grid_per_cu;
   STAGE(launch_tile_order(ws, stream), "order");
-  STAGE(launch_fused(ws, ko, targets, images, V, use_history(*plan) ? 1 : 0, plan->opt.lds_batch, grid, stream),
+  STAGE(launch_fused(ws, ko, targets, images, V, use_history(*plan) ? 1 : 0, plan->opt.lds_batch,
+                     plan->opt.bwd_reduce, grid, stream),
          "fused raster");
   STAGE(launch_project_bwd(kparams(*plan, g), cams, ko, ws, kgrads(grads), stats ? stats->grad2d_norm_sum : nullptr,
                             stats ? stats->visible_count : nullptr, -1, stream),
@@ -406,7 +408,8 @@ gsr_status enqueue_plain_l1(gsr_plan *plan, const gsr_gaussians *g, const gsr_ca
     STAGE(launch_sort(ws, vi.tile_base, nt, stream), "sort");
     STAGE(launch_raster_fwd(ws, ko, vi.tile_base, nt, images, V, hist, plan->opt.lds_batch, stream), "raster_fwd");
     STAGE(launch_l1(ws, ko, vi.tile_base, nt, images, targets, V, stream), "l1");
-    STAGE(launch_raster_bwd(ws, ko, vi.tile_base, nt, ws.pix_dLdC, V, hist, plan->opt.lds_batch, stream), "raster_bwd");
+    STAGE(launch_raster_bwd(ws, ko, vi.tile_base, nt, ws.pix_dLdC, V, hist, plan->opt.lds_batch,
+                            plan->opt.bwd_reduce, stream), "raster_bwd");
     STAGE(launch_project_bwd(kp, cams, ko, ws, kgrads(grads), stats ? stats->grad2d_norm_sum : nullptr,
                               stats ? stats->visible_count : nullptr, v, stream),
            "project_bwd");
@@ -520,6 +523,7 @@ gsr_status gsr_plan_set_tuning(gsr_plan *plan, const gsr_options *t) {
   o.bwd_variant = t->bwd_variant;
   o.lds_batch = t->lds_batch;
   o.grid_per_cu = t->grid_per_cu;
+  o.bwd_reduce = t->bwd_reduce;
   if (validate_options(o) != GSR_OK) return GSR_ERR_INVALID_ARG;
   const size_t old_bytes = plan->ws_bytes;
   const int64_t old_hist = plan->layout.history_entries;
@@ -585,11 +589,13 @@ gsr_status gsr_backward(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera
     const ViewTable tbl = view_table(*plan);
     for (int v = 0; v < V; v++) {
       const int64_t nt = (int64_t)tbl.v[v].tiles_x * tbl.v[v].tiles_y;
-      STAGE(launch_raster_bwd(k, ko, tbl.v[v].tile_base, nt, dL_dimages, V, hist, plan->opt.lds_batch, stream), "raster_bwd");
+      STAGE(launch_raster_bwd(k, ko, tbl.v[v].tile_base, nt, dL_dimages, V, hist, plan->opt.lds_batch,
+                              plan->opt.bwd_reduce, stream), "raster_bwd");
       STAGE(launch_project_bwd(kp, cams, ko, k, kgrads(grads), sS, sN, v, stream), "project_bwd");
     }
   } else {
-    STAGE(launch_raster_bwd(k, ko, 0, k.tiles_total, dL_dimages, V, hist, plan->opt.lds_batch, stream), "raster_bwd");
+    STAGE(launch_raster_bwd(k, ko, 0, k.tiles_total, dL_dimages, V, hist, plan->opt.lds_batch,
+                            plan->opt.bwd_reduce, stream), "raster_bwd");
     STAGE(launch_project_bwd(kp, cams, ko, k, kgrads(grads), sS, sN, -1, stream), "project_bwd");
   }
   plan->forward_ready = false;
@@ -708,7 +714,7 @@ gsr_status gsr_autotune(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera
   plan->capturing = true;  // no stage timing while tuning
   const int shapes[3][2] = {{16, 16}, {32, 8}, {8, 32}};
   const int batches[3] = {64, 128, 256};
-  const int grids[3] = {2, 4, 8};
+  const int grids[2] = {4, 8};
   std::vector<int> variants = {GSR_BWD_RECOMPUTE};
   if (plan->layout.history_entries > 0) variants.push_back(GSR_BWD_STORED);
   hipEvent_t e0, e1;
@@ -719,13 +725,15 @@ gsr_status gsr_autotune(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera
   for (auto &sh : shapes)
     for (int b : batches)
       for (int gpc : grids)
-        for (int var : variants) {
+        for (int var : variants)
+        for (int red = 0; red < 3; red++) {
           gsr_options o = start;
           o.tile_w = sh[0];
           o.tile_h = sh[1];
           o.lds_batch = b;
           o.grid_per_cu = gpc;
           o.bwd_variant = var;
+          o.bwd_reduce = red;
           plan->opt = o;
           compute_layout(*plan);
           if (var == GSR_BWD_STORED && plan->layout.history_entries == 0) continue;

@@ -110,9 +110,9 @@ int launch_raster_fwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t ti
 int launch_l1(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *images,
               const float *targets, int n_views, void *stream);
 int launch_raster_bwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *dLdC,
-                      int n_views, int use_history, int lds_batch, void *stream);
+                      int n_views, int use_history, int lds_batch, int red, void *stream);
 int launch_fused(const KWs &ws, const KOpts &o, const float *targets, float *images, int n_views,
-                 int use_history, int lds_batch, int grid, void *stream);
+                 int use_history, int lds_batch, int red, int grid, void *stream);
 int launch_project_bwd(const KParams &p, const gsr_camera *cams, const KOpts &o, const KWs &ws,
                        const KGrads &g, float *stat_S, uint32_t *stat_n, int view_only, void *stream);
 int launch_loss(const KWs &ws, int n_views, float *loss, void *stream);

@@ -12,10 +12,13 @@
 // to evaluating them; on city-scale scenes most entries of a tile list miss
 // most strips, which is where the time would otherwise go.
 //
-// Reverse pass.  Per kept entry, the nine 2D partials of the wave's pixels
-// are summed with DPP (no LDS), skipped entirely when no lane contributes
-// (ballot), and lanes 0..8 issue one atomic add each into the record's
-// gradient slot (nine consecutive floats of one cache line).
+// Reverse pass.  Two reductions of the nine 2D partials per entry, chosen by
+// the autotuner: DPP sums over the wavefront (skipped by ballot when no lane
+// contributes) with lanes 0..8 issuing one device atomic each into the
+// record's gradient slot (nine consecutive floats of one cache line); or LDS
+// float atomics into a per-batch accumulator that also combines the four
+// wavefronts, flushed with one device atomic per (entry, component), either
+// from every contributing lane or after DPP sums over lane quads.
 #include <hip/hip_runtime.h>
 
 #include "gsr_device.h"
@@ -151,10 +154,16 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
 // Back-to-front reverse pass of one tile.  g = dL/dC_out of this lane's
 // pixel, T its final transmittance (recovered entry by entry unless the
 // forward stored it).
-template <int B>
+//   RED = 0: per kept entry, DPP sums of the nine partials over the
+//            wavefront and one device atomic per component from lanes 0..8.
+//   RED = 1: contributing lanes add their partials into an LDS accumulator
+//            of the batch (ds_add_f32, combining the four wavefronts); one
+//            device atomic per non-zero (entry, component) after the batch.
+template <int B, int RED>
 __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsRec *s_rec,
-                                              uint32_t *s_idx, uint16_t (*s_list)[B], int *s_max, float T,
-                                              int last, const float g[3], const float *hist) {
+                                              uint32_t *s_idx, uint16_t (*s_list)[B], float (*s_acc)[9],
+                                              int *s_max, float T, int last, const float g[3],
+                                              const float *hist) {
   const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
   const int wave = threadIdx.x >> 6, lane = lane_id();
   float S[3] = {T * o.bg[0], T * o.bg[1], T * o.bg[2]};
@@ -170,6 +179,8 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
     const int nb = (int)(hi - lo);
     __syncthreads();
     load_batch(ws, lo, nb, s_rec, s_idx);
+    if (RED >= 1)
+      for (int e = threadIdx.x; e < nb * 9; e += blockDim.x) (&s_acc[0][0])[e] = 0.0f;
     __syncthreads();
     const int cnt = strip_list<B>(s_rec, nb, c, s_list[wave]);
     __syncthreads();
@@ -210,16 +221,43 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
           T = Ti;
         }
       }
-      if (__ballot(contrib) != 0ull) {
-        float mine = 0.0f;
+      if (RED == 0) {
+        if (__ballot(contrib) != 0ull) {
+          float mine = 0.0f;
 #pragma unroll
-        for (int q = 0; q < 9; q++) {
-          const float tot = __builtin_bit_cast(float, __builtin_amdgcn_readlane(
-                                                          __builtin_bit_cast(int, wave_sum_lane63(v[q])), 63));
-          mine = lane == q ? tot : mine;
+          for (int q = 0; q < 9; q++) {
+            const float tot = __builtin_bit_cast(
+                float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wave_sum_lane63(v[q])), 63));
+            mine = lane == q ? tot : mine;
+          }
+          if (lane < 9 && mine != 0.0f)
+            unsafeAtomicAdd(&ws.grad2d[(int64_t)s_idx[jj] * kGrad2dStride + lane], mine);
         }
-        if (lane < 9 && mine != 0.0f)
-          unsafeAtomicAdd(&ws.grad2d[(int64_t)s_idx[jj] * kGrad2dStride + lane], mine);
+      } else if (RED == 1) {
+        if (contrib) {
+#pragma unroll
+          for (int q = 0; q < 9; q++)
+            if (v[q] != 0.0f) atomicAdd(&s_acc[jj][q], v[q]);
+        }
+      } else {
+        // quad sums (two DPP steps), then one LDS atomic per quad and component
+        if (__ballot(contrib) != 0ull) {
+#pragma unroll
+          for (int q = 0; q < 9; q++) {
+            float x = v[q];
+            x += dpp_or_zero<0xB1>(x);  // quad_perm [1,0,3,2]
+            x += dpp_or_zero<0x4E>(x);  // quad_perm [2,3,0,1]
+            if ((lane & 3) == 0 && x != 0.0f) atomicAdd(&s_acc[jj][q], x);
+          }
+        }
+      }
+    }
+    if (RED >= 1) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < nb * 9; e += blockDim.x) {
+        const int jj = e / 9, q = e - jj * 9;
+        const float val = s_acc[jj][q];
+        if (val != 0.0f) unsafeAtomicAdd(&ws.grad2d[(int64_t)s_idx[jj] * kGrad2dStride + q], val);
       }
     }
   }
@@ -287,12 +325,13 @@ __global__ __launch_bounds__(kBlock) void k_l1(KWs ws, KOpts o, int64_t tile_lo,
   if (threadIdx.x == 0) ws.tile_loss[t] = s;
 }
 
-template <int TW, int TH, int B>
+template <int TW, int TH, int B, int RED>
 __global__ __launch_bounds__(kBlock) void k_raster_bwd(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
                                                        const float *dLdC, int n_views, int use_history) {
   __shared__ LdsRec s_rec[B];
   __shared__ uint32_t s_idx[B];
   __shared__ uint16_t s_list[4][B];
+  __shared__ float s_acc[RED >= 1 ? B : 1][9];
   __shared__ int s_max;
   __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
   for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
@@ -313,18 +352,20 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(KWs ws, KOpts o, int64_t 
     T = ws.pix_T[c.vi.pix_base + c.pix];
     last = (int)ws.pix_last[c.vi.pix_base + c.pix];
   }
-  tile_backward<B>(ws, o, c, s_rec, s_idx, s_list, &s_max, T, last, g, use_history ? ws.history : nullptr);
+  tile_backward<B, RED>(ws, o, c, s_rec, s_idx, s_list, s_acc, &s_max, T, last, g,
+                        use_history ? ws.history : nullptr);
 }
 
 // Persistent fused forward + L1 + reverse pass.  Workgroups take tiles from
 // ws.hdr->queue (in `order` when given) until the counter passes the last
 // tile; no workgroup ever waits for another.
-template <int TW, int TH, int B>
+template <int TW, int TH, int B, int RED>
 __global__ __launch_bounds__(kBlock) void k_fused(KWs ws, KOpts o, const float *targets, float *images,
                                                   int n_views, int use_history, const uint32_t *order) {
   __shared__ LdsRec s_rec[B];
   __shared__ uint32_t s_idx[B];
   __shared__ uint16_t s_list[4][B];
+  __shared__ float s_acc[RED >= 1 ? B : 1][9];
   __shared__ int s_max;
   __shared__ float s_w[4];
   __shared__ int64_t s_item;
@@ -361,7 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(KWs ws, KOpts o, const float *
     }
     const float s = block_sum_fixed(acc, s_w);
     if (threadIdx.x == 0) ws.tile_loss[t] = s;
-    tile_backward<B>(ws, o, c, s_rec, s_idx, s_list, &s_max, T, last, g, hist);
+    tile_backward<B, RED>(ws, o, c, s_rec, s_idx, s_list, s_acc, &s_max, T, last, g, hist);
   }
 }
 
@@ -437,6 +478,14 @@ int launch_tile_order(const KWs &ws, void *stream) {
     return last_err();                                                      \
   }
 
+// reverse-pass kernels also select the reduction mode
+#define GSR_RED_CALL(KER, TW_, TH_, B_, ...)                                         \
+  do {                                                                             \
+    if (red == 2) hipLaunchKernelGGL((KER<TW_, TH_, B_, 2>), grid, block, 0, s, __VA_ARGS__); \
+    else if (red == 1) hipLaunchKernelGGL((KER<TW_, TH_, B_, 1>), grid, block, 0, s, __VA_ARGS__); \
+    else hipLaunchKernelGGL((KER<TW_, TH_, B_, 0>), grid, block, 0, s, __VA_ARGS__);          \
+  } while (0)
+
 int launch_raster_fwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, float *images,
                       int n_views, int store_history, int lds_batch, void *stream) {
   if (tile_count <= 0) return 0;
@@ -461,13 +510,12 @@ int launch_l1(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count
 }
 
 int launch_raster_bwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *dLdC,
-                      int n_views, int use_history, int lds_batch, void *stream) {
+                      int n_views, int use_history, int lds_batch, int red, void *stream) {
   if (tile_count <= 0) return 0;
   const dim3 grid((unsigned)xcd_grid(tile_count)), block(kBlock);
   hipStream_t s = (hipStream_t)stream;
-#define CALL_BWD(a, b_, B)                                                                                 \
-  hipLaunchKernelGGL((k_raster_bwd<a, b_, B>), grid, block, 0, s, ws, o, tile_lo, tile_count, dLdC, n_views, \
-                     use_history)
+#define CALL_BWD(a, b_, B) \
+  GSR_RED_CALL(k_raster_bwd, a, b_, B, ws, o, tile_lo, tile_count, dLdC, n_views, use_history)
   GSR_TILE_DISPATCH(16, 16, CALL_BWD)
   GSR_TILE_DISPATCH(32, 8, CALL_BWD)
   GSR_TILE_DISPATCH(8, 32, CALL_BWD)
@@ -476,12 +524,12 @@ int launch_raster_bwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t ti
 }
 
 int launch_fused(const KWs &ws, const KOpts &o, const float *targets, float *images, int n_views, int use_history,
-                 int lds_batch, int grid_blocks, void *stream) {
+                 int lds_batch, int red, int grid_blocks, void *stream) {
   const dim3 grid((unsigned)grid_blocks), block(kBlock);
   hipStream_t s = (hipStream_t)stream;
   const uint32_t *order = ws.tile_order;
 #define CALL_FUSED(a, b_, B) \
-  hipLaunchKernelGGL((k_fused<a, b_, B>), grid, block, 0, s, ws, o, targets, images, n_views, use_history, order)
+  GSR_RED_CALL(k_fused, a, b_, B, ws, o, targets, images, n_views, use_history, order)
   GSR_TILE_DISPATCH(16, 16, CALL_FUSED)
   GSR_TILE_DISPATCH(32, 8, CALL_FUSED)
   GSR_TILE_DISPATCH(8, 32, CALL_FUSED)

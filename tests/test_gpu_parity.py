@@ -149,11 +149,12 @@ def test_records_and_binning_bit_exact(scene_name, c0, ragged):
     assert np.array_equal((keys >> 32).astype(np.uint32), b["depth"])
 
 
+@pytest.mark.parametrize("red", [0, 1, 2])
 @pytest.mark.parametrize("mode", ["plain", "batched"])
 @pytest.mark.parametrize("tile", [(16, 16), (32, 8), (8, 32)])
-def test_ragged_multiview_matches_oracle(ragged, mode, tile):
-    announce("ragged", mode, tile)
-    r, params, cams, targets, loss = run_step(ragged, mode=mode, tile=tile)
+def test_ragged_multiview_matches_oracle(ragged, mode, tile, red):
+    announce("ragged", mode, tile, "reduce", red)
+    r, params, cams, targets, loss = run_step(ragged, mode=mode, tile=tile, bwd_reduce=red)
     ora = ora_step(ragged, tile)
     rep = {}
     parity.compare_images(parity.gpu_images(r), ora, rep)
@@ -297,6 +298,17 @@ def test_counts_match_oracle(ragged):
         assert abs(c.visible[v] - int(ora["records"][v]["visible"].sum())) <= int((ora["records"][v]["margin"] < parity.DELTA).sum())
     assert c.intersections_total == r.ws_tensor("tile_start", torch.int32, r.layout.tiles_total + 1)[-1].item()
     assert c.visible_union == int(sum((r_["visible"] > 0) for r_ in ora["records"]).astype(bool).sum())
+
+
+def test_persistent_schedule_is_a_longest_first_permutation(ragged):
+    announce("tile order")
+    r, params, cams, targets, _ = run_step(ragged, mode="batched", tile=(8, 32))
+    L = r.layout
+    order = r.ws_tensor("tile_order", torch.int32, L.tiles_total).cpu().numpy()
+    assert np.array_equal(np.sort(order), np.arange(L.tiles_total))
+    starts = r.ws_tensor("tile_start", torch.int32, L.tiles_total + 1).cpu().numpy().astype(np.int64)
+    lengths = np.diff(starts)[order]
+    assert np.all(np.diff(np.minimum(lengths // 4, 1023)) <= 0)
 
 
 def test_autograd_function_returns_library_gradients(ragged):
