@@ -95,7 +95,8 @@ typedef struct gsr_options {
   int32_t bwd_reduce;     /* reverse-pass reduction: 0 = wavefront DPP sums + one device atomic per
                              (wavefront, record, component); 1 = per-lane LDS float atomics into a
                              per-batch accumulator + one device atomic per (tile, record,
-                             component); 2 = as 1 after DPP sums over lane quads */
+                             component); 2 = as 1 after DPP sums over lane quads; 3 = as 1 after
+                             DPP sums over 16-lane rows, one LDS atomic instruction per entry */
   float near_plane, far_plane;
   float eps2d;           /* low-pass dilation of the 2D covariance */
   float sigma_extent;    /* footprint radius in standard deviations */

@@ -239,6 +239,24 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
           for (int q = 0; q < 9; q++)
             if (v[q] != 0.0f) atomicAdd(&s_acc[jj][q], v[q]);
         }
+      } else if (RED == 3) {
+        // row sums (four DPP steps leave every lane of a 16-lane row with the
+        // row's total), then lane 16 row + q adds component q: one LDS atomic
+        // instruction per entry, four rows per address
+        if (__ballot(contrib) != 0ull) {
+          const int q = lane & 15;
+          float mine = 0.0f;
+#pragma unroll
+          for (int k = 0; k < 9; k++) {
+            float x = v[k];
+            x += dpp_or_zero<0xB1>(x);   // quad_perm [1,0,3,2]
+            x += dpp_or_zero<0x4E>(x);   // quad_perm [2,3,0,1]
+            x += dpp_or_zero<0x141>(x);  // row_half_mirror
+            x += dpp_or_zero<0x140>(x);  // row_mirror
+            mine = q == k ? x : mine;
+          }
+          if (q < 9 && mine != 0.0f) atomicAdd(&s_acc[jj][q], mine);
+        }
       } else {
         // quad sums (two DPP steps), then one LDS atomic per quad and component
         if (__ballot(contrib) != 0ull) {
@@ -481,7 +499,8 @@ int launch_tile_order(const KWs &ws, void *stream) {
 // reverse-pass kernels also select the reduction mode
 #define GSR_RED_CALL(KER, TW_, TH_, B_, ...)                                         \
   do {                                                                             \
-    if (red == 2) hipLaunchKernelGGL((KER<TW_, TH_, B_, 2>), grid, block, 0, s, __VA_ARGS__); \
+    if (red == 3) hipLaunchKernelGGL((KER<TW_, TH_, B_, 3>), grid, block, 0, s, __VA_ARGS__); \
+    else if (red == 2) hipLaunchKernelGGL((KER<TW_, TH_, B_, 2>), grid, block, 0, s, __VA_ARGS__); \
     else if (red == 1) hipLaunchKernelGGL((KER<TW_, TH_, B_, 1>), grid, block, 0, s, __VA_ARGS__); \
     else hipLaunchKernelGGL((KER<TW_, TH_, B_, 0>), grid, block, 0, s, __VA_ARGS__);          \
   } while (0)

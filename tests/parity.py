@@ -69,14 +69,20 @@ def compare_pixels(gpu_T, gpu_last, ora):
         assert np.array_equal(l[~amb], ora["last"][v][~amb])
 
 
-def excluded_gaussians(ora, n, opts):
+L1_KINK = 1e-5  # |image - target| below this: the L1 sign may differ (float32 image error ~1e-6)
+
+
+def excluded_gaussians(ora, n, opts, targets=None):
     """Gaussians whose gradient may differ legitimately: those listed in a tile
-    that holds an ambiguous pixel, those with an ambiguous decision of their
-    own, and those sitting on a kink (colour clamp, Jacobian clamp)."""
+    that holds an ambiguous pixel or (given the targets) a pixel on the L1
+    kink, those with an ambiguous decision of their own, and those sitting on
+    a kink (colour clamp, Jacobian clamp)."""
     ex = np.zeros(n, bool)
     vals = ora["bins"]["values"]
     ranges = ora["bins"]["ranges"]
     for v, amb in enumerate(ora["ambiguous"]):
+        if targets is not None:
+            amb = amb.astype(bool) | (np.abs(ora["images"][v] - targets[v]) < L1_KINK).any(axis=0)
         if not amb.any():
             continue
         gx, gy = ora["grids"][v]

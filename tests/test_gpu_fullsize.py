@@ -40,7 +40,7 @@ def test_config1_full_step_matches_oracle():
     rep = {}
     parity.compare_images(parity.gpu_images(r), ora, rep)
     assert abs(float(loss.item()) - ora["loss"]) <= 1e-5 * ora["loss"]
-    ex = parity.excluded_gaussians(ora, s.n, parity.opts_for((8, 32)))
+    ex = parity.excluded_gaussians(ora, s.n, parity.opts_for((8, 32)), s.targets)
     parity.compare_grads(parity.gpu_grad_groups(r.grads), ora["grads"], ex, report=rep)
     keep = ~ex
     S = r.S.cpu().numpy().astype(np.float64)

@@ -76,7 +76,7 @@ def test_config0_step_matches_oracle(c0, mode):
     T = r.ws_tensor("pix_T", torch.float32, r.pixels).cpu().numpy()
     last = r.ws_tensor("pix_last", torch.int32, r.pixels).cpu().numpy()
     parity.compare_pixels([T.reshape(128, 128)], [last.reshape(128, 128)], ora)
-    ex = parity.excluded_gaussians(ora, c0.n, parity.opts_for())
+    ex = parity.excluded_gaussians(ora, c0.n, parity.opts_for(), c0.targets)
     parity.compare_grads(parity.gpu_grad_groups(r.grads), ora["grads"], ex, report=rep)
     S = r.S.cpu().numpy().astype(np.float64)
     keep = ~ex
@@ -149,7 +149,7 @@ def test_records_and_binning_bit_exact(scene_name, c0, ragged):
     assert np.array_equal((keys >> 32).astype(np.uint32), b["depth"])
 
 
-@pytest.mark.parametrize("red", [0, 1, 2])
+@pytest.mark.parametrize("red", [0, 1, 2, 3])
 @pytest.mark.parametrize("mode", ["plain", "batched"])
 @pytest.mark.parametrize("tile", [(16, 16), (32, 8), (8, 32)])
 def test_ragged_multiview_matches_oracle(ragged, mode, tile, red):
@@ -159,7 +159,7 @@ def test_ragged_multiview_matches_oracle(ragged, mode, tile, red):
     rep = {}
     parity.compare_images(parity.gpu_images(r), ora, rep)
     assert abs(loss - ora["loss"]) <= 1e-5 * abs(ora["loss"])
-    ex = parity.excluded_gaussians(ora, ragged.n, parity.opts_for(tile))
+    ex = parity.excluded_gaussians(ora, ragged.n, parity.opts_for(tile), ragged.targets)
     parity.compare_grads(parity.gpu_grad_groups(r.grads), ora["grads"], ex, report=rep)
     print("report", rep)
 
