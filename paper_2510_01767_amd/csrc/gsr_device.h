@@ -14,12 +14,17 @@ namespace gsr {
 
 // ------------------------------------------------------------ camera, geometry
 
+// One view's camera in float64, with the per-view constants of the
+// projection computed once per workgroup (kept in LDS).
 struct Cam64 {
   double R[9], t[3], fx, fy, cx, cy;
-  int W, H;
+  double limx, limy;  // clamp of x/z and y/z inside the Jacobian
+  double itw, ith;    // 1 / tile size (powers of two, so x * itw == x / tile_w)
+  double cc[3];       // R^T t: mean + cc is the mean relative to the camera centre
+  int W, H, tiles_x, tiles_y;
 };
 
-__device__ __forceinline__ Cam64 cam64(const gsr_camera &c, int W, int H) {
+__device__ __forceinline__ Cam64 cam64(const gsr_camera &c, const ViewInfo &vi, const KOpts &o) {
   Cam64 k;
 #pragma unroll
   for (int a = 0; a < 9; a++) k.R[a] = (double)c.R[a];
@@ -29,9 +34,24 @@ __device__ __forceinline__ Cam64 cam64(const gsr_camera &c, int W, int H) {
   k.fy = c.fy;
   k.cx = c.cx;
   k.cy = c.cy;
-  k.W = W;
-  k.H = H;
+  k.W = vi.W;
+  k.H = vi.H;
+  k.tiles_x = vi.tiles_x;
+  k.tiles_y = vi.tiles_y;
+  k.limx = (double)o.jac_clamp * (0.5 * k.W / k.fx);
+  k.limy = (double)o.jac_clamp * (0.5 * k.H / k.fy);
+  k.itw = 1.0 / (double)o.tile_w;
+  k.ith = 1.0 / (double)o.tile_h;
+#pragma unroll
+  for (int a = 0; a < 3; a++) k.cc[a] = k.R[a] * k.t[0] + k.R[3 + a] * k.t[1] + k.R[6 + a] * k.t[2];
   return k;
+}
+
+// The cameras of views [0, n_views) into LDS (one per thread, then a barrier).
+__device__ __forceinline__ void load_cams(Cam64 *s_cam, const gsr_camera *cams, const ViewInfo *views, int n_views,
+                                          const KOpts &o) {
+  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_cam[v] = cam64(cams[v], views[v], o);
+  __syncthreads();
 }
 
 // View-independent part of one Gaussian.
@@ -126,8 +146,7 @@ struct Proj {
 // Cheap conservative test: false only when the Gaussian is certainly not
 // visible.  lambda_max(J W Sigma W^T J^T) <= |J|_F^2 max(s)^2, so the exact
 // tile rectangle lies inside the one built from this bound.
-__device__ __forceinline__ bool maybe_visible(const GeoF &g, const Cam64 &k, const KOpts &o, int tiles_x,
-                                              int tiles_y) {
+__device__ __forceinline__ bool maybe_visible(const GeoF &g, const Cam64 &k, const KOpts &o) {
   double tc[3];
 #pragma unroll
   for (int r = 0; r < 3; r++)
@@ -137,18 +156,17 @@ __device__ __forceinline__ bool maybe_visible(const GeoF &g, const Cam64 &k, con
   const double iz = 1.0 / tz;
   const double ux = tc[0] * iz, uy = tc[1] * iz;
   const double mx = k.fx * ux + k.cx, my = k.fy * uy + k.cy;
-  const double limx = (double)o.jac_clamp * (0.5 * k.W / k.fx);
-  const double limy = (double)o.jac_clamp * (0.5 * k.H / k.fy);
-  const double u = fmin(fabs(ux), limx), v = fmin(fabs(uy), limy);
+  const double u = fmin(fabs(ux), k.limx), v = fmin(fabs(uy), k.limy);
   const double jn2 = (k.fx * iz) * (k.fx * iz) * (1.0 + u * u) + (k.fy * iz) * (k.fy * iz) * (1.0 + v * v);
   const double rb = ceil((double)o.sigma * sqrt(jn2 * g.smax2 + (double)o.eps2d)) + 1.0;
-  return !(floor((mx + rb) / o.tile_w) < 0.0 || floor((my + rb) / o.tile_h) < 0.0 ||
-           floor((mx - rb) / o.tile_w) > tiles_x - 1 || floor((my - rb) / o.tile_h) > tiles_y - 1);
+  return !(floor((mx + rb) * k.itw) < 0.0 || floor((my + rb) * k.ith) < 0.0 ||
+           floor((mx - rb) * k.itw) > k.tiles_x - 1 || floor((my - rb) * k.ith) > k.tiles_y - 1);
 }
 
-template <class G>
-__device__ __forceinline__ bool project_view(const G &g, const Cam64 &k, const KOpts &o, int tiles_x,
-                                             int tiles_y, Proj &P) {
+// RECT = false (the reverse pass, on pairs known to be visible) stops after
+// the conic: no eigenvalue, radius or tile rectangle.
+template <bool RECT = true, class G>
+__device__ __forceinline__ bool project_view(const G &g, const Cam64 &k, const KOpts &o, Proj &P) {
 #pragma unroll
   for (int r = 0; r < 3; r++)
     P.tc[r] = k.R[r * 3 + 0] * g.mu[0] + k.R[r * 3 + 1] * g.mu[1] + k.R[r * 3 + 2] * g.mu[2] + k.t[r];
@@ -158,12 +176,10 @@ __device__ __forceinline__ bool project_view(const G &g, const Cam64 &k, const K
   const double ux = P.tc[0] * iz, uy = P.tc[1] * iz;
   P.mx = k.fx * ux + k.cx;
   P.my = k.fy * uy + k.cy;
-  const double limx = (double)o.jac_clamp * (0.5 * k.W / k.fx);
-  const double limy = (double)o.jac_clamp * (0.5 * k.H / k.fy);
-  P.cu = fabs(ux) > limx;
-  P.cv = fabs(uy) > limy;
-  P.u = P.cu ? copysign(limx, ux) : ux;
-  P.v = P.cv ? copysign(limy, uy) : uy;
+  P.cu = fabs(ux) > k.limx;
+  P.cv = fabs(uy) > k.limy;
+  P.u = P.cu ? copysign(k.limx, ux) : ux;
+  P.v = P.cv ? copysign(k.limy, uy) : uy;
   // J = [[fx/z, 0, -fx u / z], [0, fy/z, -fy v / z]];  T = J W
   const double j00 = k.fx * iz, j02 = -k.fx * P.u * iz, j11 = k.fy * iz, j12 = -k.fy * P.v * iz;
 #pragma unroll
@@ -186,17 +202,18 @@ __device__ __forceinline__ bool project_view(const G &g, const Cam64 &k, const K
   P.A = P.c * idet;
   P.B = -P.b * idet;
   P.C = P.a * idet;
+  if (!RECT) return true;
   const double hd = 0.5 * (P.a - P.c);
   const double lam = 0.5 * (P.a + P.c) + sqrt(hd * hd + P.b * P.b);
   P.lam = lam;
   const double rad = ceil((double)o.sigma * sqrt(lam));
-  const double lox = floor((P.mx - rad) / o.tile_w), hix = floor((P.mx + rad) / o.tile_w);
-  const double loy = floor((P.my - rad) / o.tile_h), hiy = floor((P.my + rad) / o.tile_h);
-  if (hix < 0.0 || hiy < 0.0 || lox > tiles_x - 1 || loy > tiles_y - 1) return false;
+  const double lox = floor((P.mx - rad) * k.itw), hix = floor((P.mx + rad) * k.itw);
+  const double loy = floor((P.my - rad) * k.ith), hiy = floor((P.my + rad) * k.ith);
+  if (hix < 0.0 || hiy < 0.0 || lox > k.tiles_x - 1 || loy > k.tiles_y - 1) return false;
   P.x0 = lox < 0.0 ? 0 : (int)lox;
   P.y0 = loy < 0.0 ? 0 : (int)loy;
-  P.x1 = hix > tiles_x - 1 ? tiles_x - 1 : (int)hix;
-  P.y1 = hiy > tiles_y - 1 ? tiles_y - 1 : (int)hiy;
+  P.x1 = hix > k.tiles_x - 1 ? k.tiles_x - 1 : (int)hix;
+  P.y1 = hiy > k.tiles_y - 1 ? k.tiles_y - 1 : (int)hiy;
   return true;
 }
 
@@ -243,47 +260,47 @@ __device__ __forceinline__ void sh_eval(T x, T y, T z, T *Y) {
 }
 
 // Gradient w.r.t. (x, y, z) of sum_k w_k Y_k (polynomial forms above).
-template <int D>
-__device__ __forceinline__ void sh_grad(double x, double y, double z, const double *w, double g[3]) {
-  g[0] = g[1] = g[2] = 0.0;
+template <int D, class T>
+__device__ __forceinline__ void sh_grad(T x, T y, T z, const T *w, T g[3]) {
+  g[0] = g[1] = g[2] = (T)0;
   if (D >= 1) {
-    g[1] += -kY1 * w[1];
-    g[2] += kY1 * w[2];
-    g[0] += -kY1 * w[3];
+    g[1] += -(T)kY1 * w[1];
+    g[2] += (T)kY1 * w[2];
+    g[0] += -(T)kY1 * w[3];
   }
   if (D >= 2) {
-    g[0] += kY2a * y * w[4];
-    g[1] += kY2a * x * w[4];
-    g[1] += -kY2a * z * w[5];
-    g[2] += -kY2a * y * w[5];
-    g[0] += -2.0 * kY2b * x * w[6];
-    g[1] += -2.0 * kY2b * y * w[6];
-    g[2] += 4.0 * kY2b * z * w[6];
-    g[0] += -kY2a * z * w[7];
-    g[2] += -kY2a * x * w[7];
-    g[0] += 2.0 * kY2c * x * w[8];
-    g[1] += -2.0 * kY2c * y * w[8];
+    g[0] += (T)kY2a * y * w[4];
+    g[1] += (T)kY2a * x * w[4];
+    g[1] += -(T)kY2a * z * w[5];
+    g[2] += -(T)kY2a * y * w[5];
+    g[0] += -(T)2 * (T)kY2b * x * w[6];
+    g[1] += -(T)2 * (T)kY2b * y * w[6];
+    g[2] += (T)4 * (T)kY2b * z * w[6];
+    g[0] += -(T)kY2a * z * w[7];
+    g[2] += -(T)kY2a * x * w[7];
+    g[0] += (T)2 * (T)kY2c * x * w[8];
+    g[1] += -(T)2 * (T)kY2c * y * w[8];
     if (D >= 3) {
-      const double xx = x * x, yy = y * y, zz = z * z;
-      g[0] += -kY3a * 6.0 * x * y * w[9];
-      g[1] += -kY3a * (3.0 * xx - 3.0 * yy) * w[9];
-      g[0] += kY3b * y * z * w[10];
-      g[1] += kY3b * x * z * w[10];
-      g[2] += kY3b * x * y * w[10];
-      g[0] += kY3c * 2.0 * x * y * w[11];
-      g[1] += -kY3c * (4.0 * zz - xx - 3.0 * yy) * w[11];
-      g[2] += -kY3c * 8.0 * y * z * w[11];
-      g[0] += -kY3d * 6.0 * x * z * w[12];
-      g[1] += -kY3d * 6.0 * y * z * w[12];
-      g[2] += kY3d * (6.0 * zz - 3.0 * xx - 3.0 * yy) * w[12];
-      g[0] += -kY3c * (4.0 * zz - 3.0 * xx - yy) * w[13];
-      g[1] += kY3c * 2.0 * x * y * w[13];
-      g[2] += -kY3c * 8.0 * x * z * w[13];
-      g[0] += kY3e * 2.0 * x * z * w[14];
-      g[1] += -kY3e * 2.0 * y * z * w[14];
-      g[2] += kY3e * (xx - yy) * w[14];
-      g[0] += -kY3a * (3.0 * xx - 3.0 * yy) * w[15];
-      g[1] += kY3a * 6.0 * x * y * w[15];
+      const T xx = x * x, yy = y * y, zz = z * z;
+      g[0] += -(T)kY3a * (T)6 * x * y * w[9];
+      g[1] += -(T)kY3a * ((T)3 * xx - (T)3 * yy) * w[9];
+      g[0] += (T)kY3b * y * z * w[10];
+      g[1] += (T)kY3b * x * z * w[10];
+      g[2] += (T)kY3b * x * y * w[10];
+      g[0] += (T)kY3c * (T)2 * x * y * w[11];
+      g[1] += -(T)kY3c * ((T)4 * zz - xx - (T)3 * yy) * w[11];
+      g[2] += -(T)kY3c * (T)8 * y * z * w[11];
+      g[0] += -(T)kY3d * (T)6 * x * z * w[12];
+      g[1] += -(T)kY3d * (T)6 * y * z * w[12];
+      g[2] += (T)kY3d * ((T)6 * zz - (T)3 * xx - (T)3 * yy) * w[12];
+      g[0] += -(T)kY3c * ((T)4 * zz - (T)3 * xx - yy) * w[13];
+      g[1] += (T)kY3c * (T)2 * x * y * w[13];
+      g[2] += -(T)kY3c * (T)8 * x * z * w[13];
+      g[0] += (T)kY3e * (T)2 * x * z * w[14];
+      g[1] += -(T)kY3e * (T)2 * y * z * w[14];
+      g[2] += (T)kY3e * (xx - yy) * w[14];
+      g[0] += -(T)kY3a * ((T)3 * xx - (T)3 * yy) * w[15];
+      g[1] += (T)kY3a * (T)6 * x * y * w[15];
     }
   }
 }
@@ -307,7 +324,11 @@ __device__ __forceinline__ PairAlpha pair_alpha(float pxc, float pyc, const floa
   // p = -(A dx^2 + C dy^2) / 2 - B dx dy
   const float quad = __fmaf_rn(r1.x * a.dx, a.dx, r1.z * a.dy * a.dy);
   const float p = __fmaf_rn(-0.5f, quad, -(r1.y * a.dx * a.dy));
-  a.G = (p > 0.0f || p < pmin) ? -1.0f : expf(p);  // G < 0 marks a skipped pair
+  // e^p as 2^(p log2 e) on the hardware exponential: for pmin <= p <= 0
+  // (|p log2 e| < 12) the rounding of the product and the instruction's own
+  // error stay below 6e-7 relative
+  const float e = __builtin_amdgcn_exp2f(p * 1.44269504088896341f);
+  a.G = (p > 0.0f || p < pmin) ? -1.0f : e;  // G < 0 marks a skipped pair
   a.raw = r1.w * a.G;
   a.alpha = fminf(alpha_max, a.raw);
   return a;

@@ -74,13 +74,10 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera *cams, KOpts o, KWs ws,
                                                     int view_lo, int view_hi, int or_bits) {
   constexpr int K = (D + 1) * (D + 1);
-  __shared__ gsr_camera s_cam[GSR_MAX_VIEWS];
+  __shared__ Cam64 s_cam[GSR_MAX_VIEWS];
   __shared__ ViewInfo s_view[GSR_MAX_VIEWS];
-  for (int v = threadIdx.x; v < p.n_views; v += blockDim.x) {
-    s_cam[v] = cams[v];
-    s_view[v] = ws.views[v];
-  }
-  __syncthreads();
+  for (int v = threadIdx.x; v < p.n_views; v += blockDim.x) s_view[v] = ws.views[v];
+  load_cams(s_cam, cams, ws.views, p.n_views, o);
   const int64_t n = p.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < n;
@@ -91,47 +88,31 @@ __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera 
   }
   GeoF g;
   if (keep) load_geo_fwd(p, i, g);
+  // reach of the alpha >= alpha_min ellipse {d : d^T Q d <= 2 ln(o / alpha_min)}
+  // is sqrt(2 ln(o / alpha_min) lambda_max); the exponent gets 1e-5 of slack
+  // (the float32 exponent and opacity are accurate to ~1e-6).  Below pmin the
+  // float32 exponent cannot give alpha >= alpha_min (same slack).
+  const double c2 = keep ? 2.0 * log(g.opac / (double)o.alpha_min) + 1e-5 : 0.0;
+  const float pmin = c2 > 0.0 ? (float)(-0.5 * c2) : 0.0f;
   uint32_t bits = (valid && or_bits) ? ws.view_bits[i] : 0u;
+  uint32_t fresh = 0u;  // views found visible by this call
   for (int v = view_lo; v < view_hi; v++) {
     const ViewInfo &vi = s_view[v];
-    const Cam64 cam = cam64(s_cam[v], vi.W, vi.H);
+    const Cam64 &cam = s_cam[v];
     Proj P;
     // the exact projection only where the conservative bound leaves a chance
-    const bool vis = keep && maybe_visible(g, cam, o, vi.tiles_x, vi.tiles_y) &&
-                     project_view(g, cam, o, vi.tiles_x, vi.tiles_y, P);
+    const bool vis = keep && maybe_visible(g, cam, o) && project_view(g, cam, o, P);
     if (!vis) continue;
-    bits |= 1u << v;
-    // colour: SH (float32) in the direction from the camera centre c = -R^T t to the mean
-    double d[3];
-#pragma unroll
-    for (int a = 0; a < 3; a++)
-      d[a] = g.mu[a] + (cam.R[a] * cam.t[0] + cam.R[3 + a] * cam.t[1] + cam.R[6 + a] * cam.t[2]);
-    const double idn = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    float Y[K];
-    sh_eval<D, float>((float)(d[0] * idn), (float)(d[1] * idn), (float)(d[2] * idn), Y);
-    float col[3];
-#pragma unroll
-    for (int ch = 0; ch < 3; ch++) {
-      float acc = 0.5f;
-#pragma unroll
-      for (int k = 0; k < K; k++) acc = __fmaf_rn(p.sh[(int64_t)(k * 3 + ch) * n + i], Y[k], acc);
-      col[ch] = acc > 0.0f ? acc : 0.0f;
-    }
+    fresh |= 1u << v;
     const int64_t r = (int64_t)v * n + i;
     float4 *rec = reinterpret_cast<float4 *>(ws.records) + r * kRecordFloat4;
     const float mxh = (float)P.mx, myh = (float)P.my;
     rec[0] = make_float4(mxh, myh, (float)(P.mx - (double)mxh), (float)(P.my - (double)myh));
     rec[1] = make_float4((float)P.A, (float)P.B, (float)P.C, (float)g.opac);
-    // reach of the alpha >= alpha_min ellipse {d : d^T Q d <= 2 ln(o / alpha_min)}:
-    // sqrt(2 ln(o / alpha_min) lambda_max).  The exponent gets 1e-5 of slack
-    // (the float32 exponent and opacity are accurate to ~1e-6) and the reach
-    // a relative and an absolute pad, so no pixel that the float32 alpha test
-    // accepts lies outside it; -1 when even the centre cannot reach alpha_min.
-    const double c2 = 2.0 * log(g.opac / (double)o.alpha_min) + 1e-5;
+    // the reach gets a relative and an absolute pad, so no pixel that the
+    // float32 alpha test accepts lies outside it; -1 when even the centre
+    // cannot reach alpha_min
     const float reach = c2 > 0.0 ? (float)(sqrt(c2 * P.lam) * 1.001 + 0.01) : -1.0f;
-    // below pmin the float32 exponent cannot give alpha >= alpha_min (same slack)
-    const float pmin = c2 > 0.0 ? (float)(-0.5 * c2) : 0.0f;
-    rec[2] = make_float4(col[0], col[1], col[2], pmin);
     uint4 r3 = make_uint4((uint32_t)P.x0 | ((uint32_t)P.y0 << 16), (uint32_t)P.x1 | ((uint32_t)P.y1 << 16),
                           __float_as_uint((float)P.tc[2]), __float_as_uint(reach));
     reinterpret_cast<uint4 *>(rec)[3] = r3;
@@ -160,7 +141,33 @@ __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera 
       }
     reinterpret_cast<uint4 *>(ws.ranks)[r] = rk;
   }
-  if (valid) ws.view_bits[i] = bits;
+  if (valid) ws.view_bits[i] = bits | fresh;
+  if (fresh == 0u) return;
+  // Colour of every visible view: SH (float32) in the direction from the
+  // camera centre c = -R^T t to the mean.  The coefficients are read once.
+  float sh[3 * K];
+#pragma unroll
+  for (int k = 0; k < 3 * K; k++) sh[k] = p.sh[(int64_t)k * n + i];
+  for (uint32_t b = fresh; b; b &= b - 1) {
+    const int v = __ffs(b) - 1;
+    const Cam64 &cam = s_cam[v];
+    double d[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) d[a] = g.mu[a] + cam.cc[a];
+    const double idn = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    float Y[K];
+    sh_eval<D, float>((float)(d[0] * idn), (float)(d[1] * idn), (float)(d[2] * idn), Y);
+    float col[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) {
+      float acc = 0.5f;
+#pragma unroll
+      for (int k = 0; k < K; k++) acc = __fmaf_rn(sh[k * 3 + ch], Y[k], acc);
+      col[ch] = acc > 0.0f ? acc : 0.0f;
+    }
+    const int64_t r = (int64_t)v * n + i;
+    reinterpret_cast<float4 *>(ws.records)[r * kRecordFloat4 + 2] = make_float4(col[0], col[1], col[2], pmin);
+  }
 }
 
 // Per-view visible counts and the union, from view_bits (run on demand by the
@@ -416,13 +423,8 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(KParams p, const gsr_cam
                                                         KGrads gr, float *stat_S, uint32_t *stat_n,
                                                         int view_only) {
   constexpr int K = (D + 1) * (D + 1);
-  __shared__ gsr_camera s_cam[GSR_MAX_VIEWS];
-  __shared__ ViewInfo s_view[GSR_MAX_VIEWS];
-  for (int v = threadIdx.x; v < p.n_views; v += blockDim.x) {
-    s_cam[v] = cams[v];
-    s_view[v] = ws.views[v];
-  }
-  __syncthreads();
+  __shared__ Cam64 s_cam[GSR_MAX_VIEWS];
+  load_cams(s_cam, cams, ws.views, p.n_views, o);
   const int64_t n = p.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -438,62 +440,24 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(KParams p, const gsr_cam
     }
     return;
   }
-  Geo g;
-  load_geo(p, i, g);
-  float sh[3 * K];
-#pragma unroll
-  for (int k = 0; k < 3 * K; k++) sh[k] = p.sh[(int64_t)k * n + i];
+  // the view loop needs the mean and the covariance only; the rest of the
+  // geometry is rebuilt after it (bit-identical, from the same helper)
+  GeoF gf;
+  load_geo_fwd(p, i, gf);
   double gmu[3] = {0, 0, 0}, gSig[6] = {0, 0, 0, 0, 0, 0}, gopac = 0.0;
-  float gsh[3 * K];
-#pragma unroll
-  for (int k = 0; k < 3 * K; k++) gsh[k] = 0.f;
   float Sacc = 0.f;
   uint32_t cnt = 0;
   const double stat_scale = o.stat_scale;
-  while (bits) {
-    const int v = __ffs(bits) - 1;
-    bits &= bits - 1;
-    const ViewInfo &vi = s_view[v];
-    const Cam64 cam = cam64(s_cam[v], vi.W, vi.H);
+  for (uint32_t b = bits; b; b &= b - 1) {
+    const int v = __ffs(b) - 1;
+    const Cam64 &cam = s_cam[v];
     Proj P;
-    project_view(g, cam, o, vi.tiles_x, vi.tiles_y, P);  // visible by construction of view_bits
+    project_view<false>(gf, cam, o, P);  // visible by construction of view_bits
     const float4 *g2 = reinterpret_cast<const float4 *>(ws.grad2d + ((int64_t)v * n + i) * kGrad2dStride);
-    const float4 q0 = g2[0], q1 = g2[1], q2 = g2[2];
+    const float4 q0 = g2[0], q1 = g2[1];
     const double gmx = q0.x, gmy = q0.y, gA = q0.z, gB = q0.w, gC = q1.x, go = q1.y;
-    const double gcol[3] = {q1.z, q1.w, q2.x};
     Sacc += (float)(stat_scale * sqrt(gmx * gmx + gmy * gmy));
     cnt += 1;
-    // colour -> SH coefficients and viewing direction
-    double d[3];
-#pragma unroll
-    for (int a = 0; a < 3; a++) d[a] = g.mu[a] + (cam.R[a] * cam.t[0] + cam.R[3 + a] * cam.t[1] + cam.R[6 + a] * cam.t[2]);
-    const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    const double x = d[0] / dn, y = d[1] / dn, z = d[2] / dn;
-    double Y[K];
-    sh_eval<D>(x, y, z, Y);
-    double wk[K];
-#pragma unroll
-    for (int k = 0; k < K; k++) wk[k] = 0.0;
-#pragma unroll
-    for (int ch = 0; ch < 3; ch++) {
-      double raw = 0.5;
-#pragma unroll
-      for (int k = 0; k < K; k++) raw += (double)sh[k * 3 + ch] * Y[k];
-      const double gr_ch = raw > 0.0 ? gcol[ch] : 0.0;
-#pragma unroll
-      for (int k = 0; k < K; k++) {
-        gsh[k * 3 + ch] += (float)(gr_ch * Y[k]);
-        wk[k] += gr_ch * (double)sh[k * 3 + ch];
-      }
-    }
-    if (D > 0) {
-      double gd[3];
-      sh_grad<D>(x, y, z, wk, gd);
-      const double dot = gd[0] * x + gd[1] * y + gd[2] * z;
-      gmu[0] += (gd[0] - dot * x) / dn;
-      gmu[1] += (gd[1] - dot * y) / dn;
-      gmu[2] += (gd[2] - dot * z) / dn;
-    }
     gopac += go;
     // conic -> 2D covariance:  dL/dS = -Q G_Q Q with G_Q = [[gA, gB/2], [gB/2, gC]]
     const double QA = P.A, QB = P.B, QC = P.C;
@@ -520,8 +484,8 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(KParams p, const gsr_cam
     double ST0[3], ST1[3];
 #pragma unroll
     for (int r = 0; r < 3; r++) {
-      ST0[r] = sig_at(g.Sig, r, 0) * T0[0] + sig_at(g.Sig, r, 1) * T0[1] + sig_at(g.Sig, r, 2) * T0[2];
-      ST1[r] = sig_at(g.Sig, r, 0) * T1[0] + sig_at(g.Sig, r, 1) * T1[1] + sig_at(g.Sig, r, 2) * T1[2];
+      ST0[r] = sig_at(gf.Sig, r, 0) * T0[0] + sig_at(gf.Sig, r, 1) * T0[1] + sig_at(gf.Sig, r, 2) * T0[2];
+      ST1[r] = sig_at(gf.Sig, r, 0) * T1[0] + sig_at(gf.Sig, r, 1) * T1[1] + sig_at(gf.Sig, r, 2) * T1[2];
     }
     double GT0[3], GT1[3];
 #pragma unroll
@@ -562,6 +526,53 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(KParams p, const gsr_cam
 #pragma unroll
     for (int a = 0; a < 3; a++) gmu[a] += cam.R[a] * gt[0] + cam.R[3 + a] * gt[1] + cam.R[6 + a] * gt[2];
   }
+  // colour -> SH coefficients and viewing direction, per visible view.  The
+  // forward's float32 colour is replayed operation for operation, so the
+  // clamp at zero takes the same decision here.
+  float sh[3 * K], gsh[3 * K];
+#pragma unroll
+  for (int k = 0; k < 3 * K; k++) {
+    sh[k] = p.sh[(int64_t)k * n + i];
+    gsh[k] = 0.f;
+  }
+  for (uint32_t b = bits; b; b &= b - 1) {
+    const int v = __ffs(b) - 1;
+    const Cam64 &cam = s_cam[v];
+    const float *g2 = ws.grad2d + ((int64_t)v * n + i) * kGrad2dStride;
+    const float gcol[3] = {g2[6], g2[7], g2[8]};
+    double d[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) d[a] = gf.mu[a] + cam.cc[a];
+    const double idn = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const float x = (float)(d[0] * idn), y = (float)(d[1] * idn), z = (float)(d[2] * idn);
+    float Y[K];
+    sh_eval<D, float>(x, y, z, Y);
+    float wk[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) wk[k] = 0.0f;
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) {
+      float raw = 0.5f;
+#pragma unroll
+      for (int k = 0; k < K; k++) raw = __fmaf_rn(sh[k * 3 + ch], Y[k], raw);
+      const float gr_ch = raw > 0.0f ? gcol[ch] : 0.0f;
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        gsh[k * 3 + ch] += gr_ch * Y[k];
+        wk[k] += gr_ch * sh[k * 3 + ch];
+      }
+    }
+    if (D > 0) {
+      float gd[3];
+      sh_grad<D, float>(x, y, z, wk, gd);
+      const float dot = gd[0] * x + gd[1] * y + gd[2] * z;
+      gmu[0] += (double)(gd[0] - dot * x) * idn;
+      gmu[1] += (double)(gd[1] - dot * y) * idn;
+      gmu[2] += (double)(gd[2] - dot * z) * idn;
+    }
+  }
+  Geo g;
+  load_geo(p, i, g);
   // Sigma = Rq diag(s^2) Rq^T  (gSig holds dL/dSigma_ij for i <= j, off-diagonals doubled)
   double G[9];
   {
@@ -636,13 +647,8 @@ __global__ __launch_bounds__(kBlock) void k_visibility(KParams p, const gsr_came
                                                        float bx0, float by0, float bz0, float bx1, float by1,
                                                        float bz1, uint32_t *bits_out, uint8_t *keep_out,
                                                        uint8_t *in_block) {
-  __shared__ gsr_camera s_cam[GSR_MAX_VIEWS];
-  __shared__ ViewInfo s_view[GSR_MAX_VIEWS];
-  for (int v = threadIdx.x; v < p.n_views; v += blockDim.x) {
-    s_cam[v] = cams[v];
-    s_view[v] = ws.views[v];
-  }
-  __syncthreads();
+  __shared__ Cam64 s_cam[GSR_MAX_VIEWS];
+  load_cams(s_cam, cams, ws.views, p.n_views, o);
   const int64_t n = p.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -652,11 +658,8 @@ __global__ __launch_bounds__(kBlock) void k_visibility(KParams p, const gsr_came
     GeoF g;
     load_geo_fwd(p, i, g);
     for (int v = 0; v < p.n_views; v++) {
-      const ViewInfo &vi = s_view[v];
-      const Cam64 cam = cam64(s_cam[v], vi.W, vi.H);
       Proj P;
-      if (maybe_visible(g, cam, o, vi.tiles_x, vi.tiles_y) && project_view(g, cam, o, vi.tiles_x, vi.tiles_y, P))
-        bits |= 1u << v;
+      if (maybe_visible(g, s_cam[v], o) && project_view(g, s_cam[v], o, P)) bits |= 1u << v;
     }
   }
   if (bits_out) bits_out[i] = bits;

@@ -66,14 +66,39 @@ struct LdsRec {
 };
 
 // Can the entry's alpha reach alpha_min at some pixel centre of this lane's
-// wavefront strip?  (Circle of radius `reach` against the strip's box.)
+// wavefront strip?  Two tests against the box of the strip's pixel centres:
+// the circle of radius `reach`, then the ellipse itself.  alpha >= alpha_min
+// needs q(d) = A dx^2 + 2 B dx dy + C dy^2 <= c2 = 2 ln(o / alpha_min)
+// (= -2 pmin, slack included).  q is convex with its minimum 0 at the mean,
+// so over a box that does not hold the mean its minimum lies on an edge that
+// faces the mean, where q is a 1D quadratic minimised in closed form.  The
+// box offsets are formed like the per-pixel offsets ((centre - hi) - lo), so
+// they differ from what a pixel evaluates only by relative roundings of a
+// few 1e-7; the threshold carries 1e-4 relative and absolute on top.
 __device__ __forceinline__ bool reaches_strip(const LdsRec &R, const TileCtx &c) {
   const float reach = R.reach;
   if (reach < 0.0f) return false;
   const float mx = R.r0.x + R.r0.z, my = R.r0.y + R.r0.w;
   const float ddx = fmaxf(0.0f, fmaxf(c.wx0 - mx, mx - c.wx1));
   const float ddy = fmaxf(0.0f, fmaxf(c.wy0 - my, my - c.wy1));
-  return ddx * ddx + ddy * ddy <= reach * reach;
+  if (ddx * ddx + ddy * ddy > reach * reach) return false;
+  const float x0 = (c.wx0 - R.r0.x) - R.r0.z, x1 = (c.wx1 - R.r0.x) - R.r0.z;
+  const float y0 = (c.wy0 - R.r0.y) - R.r0.w, y1 = (c.wy1 - R.r0.y) - R.r0.w;
+  const bool out_x = x0 > 0.0f || x1 < 0.0f, out_y = y0 > 0.0f || y1 < 0.0f;
+  if (!out_x && !out_y) return true;
+  const float A = R.r1.x, Bc = R.r1.y, Cc = R.r1.z;
+  float qmin = 3.0e38f;
+  if (out_x) {
+    const float X = x0 > 0.0f ? x0 : x1;
+    const float Y = fminf(fmaxf(-Bc * X / Cc, y0), y1);
+    qmin = fminf(qmin, A * X * X + 2.0f * Bc * X * Y + Cc * Y * Y);
+  }
+  if (out_y) {
+    const float Y = y0 > 0.0f ? y0 : y1;
+    const float X = fminf(fmaxf(-Bc * Y / A, x0), x1);
+    qmin = fminf(qmin, A * X * X + 2.0f * Bc * X * Y + Cc * Y * Y);
+  }
+  return qmin <= -2.0f * R.r2.w * 1.0001f + 1e-4f;
 }
 
 __device__ __forceinline__ void load_batch(const KWs &ws, int64_t lo, int nb, LdsRec *s_rec, uint32_t *s_idx) {
@@ -103,14 +128,24 @@ __device__ __forceinline__ int strip_list(const LdsRec *s_rec, int nb, const Til
   return cnt;
 }
 
+// The batch that a tile pass left in LDS: entries [lo, lo + nb) of the list
+// in s_rec (and s_idx), and this wavefront's culled list of it (cnt entries
+// in s_list).  nb == 0: nothing usable.
+struct Resident {
+  int64_t lo;
+  int nb, cnt;
+};
+
 // Front-to-back compositing of one tile.  Returns the colour, the final
 // transmittance and `last` (list entries processed before the stop, or the
-// list length).  With hist != nullptr it stores, for every evaluated entry,
-// the transmittance in front of it (0 when the entry was skipped).
-template <int B>
+// list length).  With HIST it stores, for every evaluated entry, the
+// transmittance in front of it (0 when the entry was skipped).  Batches
+// start at c.start + k B; the last one loaded stays resident (`res`).  The
+// pair update is branch-free: a skipped pair adds 0 * colour and keeps T.
+template <int B, bool HIST>
 __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsRec *s_rec,
-                                             uint16_t (*s_list)[B], float C[3], float &T, int &last,
-                                             float *hist) {
+                                             uint32_t *s_idx, uint16_t (*s_list)[B], float C[3], float &T,
+                                             int &last, float *hist, Resident &res) {
   const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
   const int wave = threadIdx.x >> 6;
   T = 1.0f;
@@ -118,34 +153,34 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
   bool done = !c.inside;
   bool stopped = false;
   last = 0;
+  res.nb = 0;
   for (int64_t b = c.start; b < c.end; b += B) {
     if (__syncthreads_and(done)) break;
     const int nb = (int)min((int64_t)B, c.end - b);
-    load_batch(ws, b, nb, s_rec, nullptr);
+    load_batch(ws, b, nb, s_rec, s_idx);
     __syncthreads();
     const int cnt = strip_list<B>(s_rec, nb, c, s_list[wave]);
     __syncthreads();
+    res.lo = b;
+    res.nb = nb;
+    res.cnt = cnt;
     for (int k = 0; k < cnt && !done; k++) {
       const int j = s_list[wave][k];
       const LdsRec &R = s_rec[j];
       const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, o.alpha_max);
-      float Tin = 0.0f;
-      if (a.alpha >= o.alpha_min) {
-        const float Tn = T * (1.0f - a.alpha);
-        if (Tn < o.T_min) {
-          done = true;
-          stopped = true;
-          last = (int)(b + j - c.start);
-          break;
-        }
-        const float w = a.alpha * T;
-        C[0] = __fmaf_rn(w, R.r2.x, C[0]);
-        C[1] = __fmaf_rn(w, R.r2.y, C[1]);
-        C[2] = __fmaf_rn(w, R.r2.z, C[2]);
-        Tin = T;
-        T = Tn;
-      }
-      if (hist) hist[(b + j) * 256 + threadIdx.x] = Tin;
+      const bool hit = a.alpha >= o.alpha_min;
+      const float Tn = T * (1.0f - a.alpha);
+      const bool stop = hit && Tn < o.T_min;
+      const bool take = hit && !stop;
+      const float w = take ? a.alpha * T : 0.0f;
+      C[0] = __fmaf_rn(w, R.r2.x, C[0]);
+      C[1] = __fmaf_rn(w, R.r2.y, C[1]);
+      C[2] = __fmaf_rn(w, R.r2.z, C[2]);
+      if (HIST && !stop) hist[(b + j) * 256 + threadIdx.x] = take ? T : 0.0f;
+      T = take ? Tn : T;
+      last = stop ? (int)(b + j - c.start) : last;
+      stopped = stopped || stop;
+      done = stop;
     }
   }
   if (!stopped) last = c.inside ? (int)(c.end - c.start) : 0;
@@ -159,11 +194,14 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
 //   RED = 1: contributing lanes add their partials into an LDS accumulator
 //            of the batch (ds_add_f32, combining the four wavefronts); one
 //            device atomic per non-zero (entry, component) after the batch.
-template <int B, int RED>
+// Batches are aligned like the forward's (c.start + k B), so when the
+// forward's last batch `res` is the first one needed here it is used as it
+// sits in LDS, culled lists included.
+template <int B, int RED, bool HIST>
 __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsRec *s_rec,
                                               uint32_t *s_idx, uint16_t (*s_list)[B], float (*s_acc)[9],
                                               int *s_max, float T, int last, const float g[3],
-                                              const float *hist) {
+                                              const float *hist, Resident res) {
   const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
   const int wave = threadIdx.x >> 6, lane = lane_id();
   float S[3] = {T * o.bg[0], T * o.bg[1], T * o.bg[2]};
@@ -173,66 +211,73 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
   __syncthreads();
   if (active && last > 0) atomicMax(s_max, last);
   __syncthreads();
-  const int64_t hi0 = c.start + *s_max;
-  for (int64_t hi = hi0; hi > c.start; hi -= B) {
-    const int64_t lo = max(c.start, hi - B);
-    const int nb = (int)(hi - lo);
+  const int top = *s_max;  // entries [0, top) of the list can contribute
+  for (int64_t lo = c.start + (int64_t)((top - 1) / B) * B; top > 0 && lo >= c.start; lo -= B) {
+    const int nb_top = (int)min((int64_t)B, c.start + top - lo);
+    int nb, cnt;
     __syncthreads();
-    load_batch(ws, lo, nb, s_rec, s_idx);
-    if (RED >= 1)
-      for (int e = threadIdx.x; e < nb * 9; e += blockDim.x) (&s_acc[0][0])[e] = 0.0f;
-    __syncthreads();
-    const int cnt = strip_list<B>(s_rec, nb, c, s_list[wave]);
-    __syncthreads();
+    if (res.nb > 0 && res.lo == lo) {
+      // the forward's last batch, still in LDS with this wavefront's list
+      nb = res.nb;
+      cnt = res.cnt;
+      res.nb = 0;
+      if (RED >= 1)
+        for (int e = threadIdx.x; e < nb * 9; e += blockDim.x) (&s_acc[0][0])[e] = 0.0f;
+      __syncthreads();
+    } else {
+      nb = nb_top;
+      load_batch(ws, lo, nb, s_rec, s_idx);
+      if (RED >= 1)
+        for (int e = threadIdx.x; e < nb * 9; e += blockDim.x) (&s_acc[0][0])[e] = 0.0f;
+      __syncthreads();
+      cnt = strip_list<B>(s_rec, nb, c, s_list[wave]);
+      __syncthreads();
+    }
+    // entries at or past `top` contribute to no pixel
+    while (cnt > 0 && (int)s_list[wave][cnt - 1] >= nb_top) cnt--;
     for (int k = cnt - 1; k >= 0; k--) {
       const int jj = s_list[wave][k];
       const int64_t j = lo + jj;
+      const LdsRec &R = s_rec[jj];
+      const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, o.alpha_max);
+      const bool contrib = active && (int)(j - c.start) < last && a.alpha >= o.alpha_min;
+      if (__ballot(contrib) == 0ull) continue;
+      // Every lane evaluates the partials (all finite: alpha <= 0.99); the
+      // non-contributing ones get zero weights, so they add exact zeros.
+      // 1 / (1 - alpha) by the hardware reciprocal (1 ulp): T and the
+      // suffix only feed gradients, never a discrete decision.
+      const float inv_om = __builtin_amdgcn_rcpf(1.0f - a.alpha);
+      const float Ti = HIST ? (contrib ? hist[j * 256 + threadIdx.x] : T) : T * inv_om;
+      const float wgt = contrib ? a.alpha * Ti : 0.0f;
+      const float col[3] = {R.r2.x, R.r2.y, R.r2.z};
       float v[9];
+      float dLda = 0.0f;
 #pragma unroll
-      for (int q = 0; q < 9; q++) v[q] = 0.0f;
-      bool contrib = false;
-      if (active && (int)(j - c.start) < last) {
-        const LdsRec &R = s_rec[jj];
-        const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, o.alpha_max);
-        if (a.alpha >= o.alpha_min) {
-          // 1 / (1 - alpha) by the hardware reciprocal (1 ulp): T and the
-          // suffix only feed gradients, never a discrete decision
-          const float inv_om = __builtin_amdgcn_rcpf(1.0f - a.alpha);
-          const float Ti = hist ? hist[j * 256 + threadIdx.x] : T * inv_om;
-          const float wgt = a.alpha * Ti;
-          const float col[3] = {R.r2.x, R.r2.y, R.r2.z};
-          float dLda = 0.0f;
-#pragma unroll
-          for (int ch = 0; ch < 3; ch++) {
-            dLda += g[ch] * (Ti * col[ch] - S[ch] * inv_om);
-            v[6 + ch] = g[ch] * wgt;
-            S[ch] = __fmaf_rn(wgt, col[ch], S[ch]);
-          }
-          if (a.raw < o.alpha_max) {
-            const float gp = dLda * a.alpha;  // dL/dp
-            v[5] = dLda * a.G;
-            v[0] = gp * __fmaf_rn(R.r1.x, a.dx, R.r1.y * a.dy);
-            v[1] = gp * __fmaf_rn(R.r1.y, a.dx, R.r1.z * a.dy);
-            v[2] = -0.5f * gp * a.dx * a.dx;
-            v[3] = -gp * a.dx * a.dy;
-            v[4] = -0.5f * gp * a.dy * a.dy;
-          }
-          contrib = true;
-          T = Ti;
-        }
+      for (int ch = 0; ch < 3; ch++) {
+        dLda += g[ch] * (Ti * col[ch] - S[ch] * inv_om);
+        v[6 + ch] = g[ch] * wgt;
+        S[ch] = __fmaf_rn(wgt, col[ch], S[ch]);
       }
+      // the geometric partials vanish where alpha is clamped at alpha_max
+      const float dLdam = (contrib && a.raw < o.alpha_max) ? dLda : 0.0f;
+      const float gp = dLdam * a.alpha;  // dL/dp
+      v[5] = dLdam * a.G;
+      v[0] = gp * __fmaf_rn(R.r1.x, a.dx, R.r1.y * a.dy);
+      v[1] = gp * __fmaf_rn(R.r1.y, a.dx, R.r1.z * a.dy);
+      v[2] = -0.5f * gp * a.dx * a.dx;
+      v[3] = -gp * a.dx * a.dy;
+      v[4] = -0.5f * gp * a.dy * a.dy;
+      T = contrib ? Ti : T;
       if (RED == 0) {
-        if (__ballot(contrib) != 0ull) {
-          float mine = 0.0f;
+        float mine = 0.0f;
 #pragma unroll
-          for (int q = 0; q < 9; q++) {
-            const float tot = __builtin_bit_cast(
-                float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wave_sum_lane63(v[q])), 63));
-            mine = lane == q ? tot : mine;
-          }
-          if (lane < 9 && mine != 0.0f)
-            unsafeAtomicAdd(&ws.grad2d[(int64_t)s_idx[jj] * kGrad2dStride + lane], mine);
+        for (int q = 0; q < 9; q++) {
+          const float tot = __builtin_bit_cast(
+              float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wave_sum_lane63(v[q])), 63));
+          mine = lane == q ? tot : mine;
         }
+        if (lane < 9 && mine != 0.0f)
+          unsafeAtomicAdd(&ws.grad2d[(int64_t)s_idx[jj] * kGrad2dStride + lane], mine);
       } else if (RED == 1) {
         if (contrib) {
 #pragma unroll
@@ -243,31 +288,30 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
         // row sums (four DPP steps leave every lane of a 16-lane row with the
         // row's total), then lane 16 row + q adds component q: one LDS atomic
         // instruction per entry, four rows per address
-        if (__ballot(contrib) != 0ull) {
-          const int q = lane & 15;
-          float mine = 0.0f;
+        // (the nine chains interleaved step by step, so no DPP result is
+        // read back-to-back)
 #pragma unroll
-          for (int k = 0; k < 9; k++) {
-            float x = v[k];
-            x += dpp_or_zero<0xB1>(x);   // quad_perm [1,0,3,2]
-            x += dpp_or_zero<0x4E>(x);   // quad_perm [2,3,0,1]
-            x += dpp_or_zero<0x141>(x);  // row_half_mirror
-            x += dpp_or_zero<0x140>(x);  // row_mirror
-            mine = q == k ? x : mine;
-          }
-          if (q < 9 && mine != 0.0f) atomicAdd(&s_acc[jj][q], mine);
-        }
+        for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0xB1>(v[q]);   // quad_perm [1,0,3,2]
+#pragma unroll
+        for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0x4E>(v[q]);   // quad_perm [2,3,0,1]
+#pragma unroll
+        for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0x141>(v[q]);  // row_half_mirror
+#pragma unroll
+        for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0x140>(v[q]);  // row_mirror
+        const int q = lane & 15;
+        float mine = v[0];
+#pragma unroll
+        for (int k = 1; k < 9; k++) mine = q == k ? v[k] : mine;
+        if (q < 9 && mine != 0.0f) atomicAdd(&s_acc[jj][q], mine);
       } else {
         // quad sums (two DPP steps), then one LDS atomic per quad and component
-        if (__ballot(contrib) != 0ull) {
 #pragma unroll
-          for (int q = 0; q < 9; q++) {
-            float x = v[q];
-            x += dpp_or_zero<0xB1>(x);  // quad_perm [1,0,3,2]
-            x += dpp_or_zero<0x4E>(x);  // quad_perm [2,3,0,1]
-            if ((lane & 3) == 0 && x != 0.0f) atomicAdd(&s_acc[jj][q], x);
-          }
-        }
+        for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0xB1>(v[q]);  // quad_perm [1,0,3,2]
+#pragma unroll
+        for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0x4E>(v[q]);  // quad_perm [2,3,0,1]
+#pragma unroll
+        for (int q = 0; q < 9; q++)
+          if ((lane & 3) == 0 && v[q] != 0.0f) atomicAdd(&s_acc[jj][q], v[q]);
       }
     }
     if (RED >= 1) {
@@ -290,9 +334,9 @@ __device__ __forceinline__ float block_sum_fixed(float x, float *s_w) {
   return r;
 }
 
-template <int TW, int TH, int B>
+template <int TW, int TH, int B, bool HIST>
 __global__ __launch_bounds__(kBlock) void k_raster_fwd(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
-                                                       float *images, int n_views, int store_history) {
+                                                       float *images, int n_views) {
   __shared__ LdsRec s_rec[B];
   __shared__ uint16_t s_list[4][B];
   __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
@@ -304,7 +348,8 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(KWs ws, KOpts o, int64_t 
   tile_ctx<TW, TH>(ws, s_views, n_views, tile_lo + b, c);
   float C[3], T;
   int last;
-  tile_forward<B>(ws, o, c, s_rec, s_list, C, T, last, store_history ? ws.history : nullptr);
+  Resident res;
+  tile_forward<B, HIST>(ws, o, c, s_rec, nullptr, s_list, C, T, last, ws.history, res);
   if (c.inside) {
     const int64_t P = (int64_t)c.vi.W * c.vi.H;
     float *img = images + c.vi.pix_base * 3;
@@ -343,9 +388,9 @@ __global__ __launch_bounds__(kBlock) void k_l1(KWs ws, KOpts o, int64_t tile_lo,
   if (threadIdx.x == 0) ws.tile_loss[t] = s;
 }
 
-template <int TW, int TH, int B, int RED>
+template <int TW, int TH, int B, int RED, bool HIST>
 __global__ __launch_bounds__(kBlock) void k_raster_bwd(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
-                                                       const float *dLdC, int n_views, int use_history) {
+                                                       const float *dLdC, int n_views) {
   __shared__ LdsRec s_rec[B];
   __shared__ uint32_t s_idx[B];
   __shared__ uint16_t s_list[4][B];
@@ -370,16 +415,16 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(KWs ws, KOpts o, int64_t 
     T = ws.pix_T[c.vi.pix_base + c.pix];
     last = (int)ws.pix_last[c.vi.pix_base + c.pix];
   }
-  tile_backward<B, RED>(ws, o, c, s_rec, s_idx, s_list, s_acc, &s_max, T, last, g,
-                        use_history ? ws.history : nullptr);
+  tile_backward<B, RED, HIST>(ws, o, c, s_rec, s_idx, s_list, s_acc, &s_max, T, last, g, ws.history,
+                              Resident{0, 0, 0});
 }
 
 // Persistent fused forward + L1 + reverse pass.  Workgroups take tiles from
 // ws.hdr->queue (in `order` when given) until the counter passes the last
 // tile; no workgroup ever waits for another.
-template <int TW, int TH, int B, int RED>
+template <int TW, int TH, int B, int RED, bool HIST>
 __global__ __launch_bounds__(kBlock) void k_fused(KWs ws, KOpts o, const float *targets, float *images,
-                                                  int n_views, int use_history, const uint32_t *order) {
+                                                  int n_views, const uint32_t *order) {
   __shared__ LdsRec s_rec[B];
   __shared__ uint32_t s_idx[B];
   __shared__ uint16_t s_list[4][B];
@@ -389,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(KWs ws, KOpts o, const float *
   __shared__ int64_t s_item;
   __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
   for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
-  float *hist = use_history ? ws.history : nullptr;
+  float *hist = ws.history;
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(&ws.hdr->queue, 1u);
@@ -401,7 +446,8 @@ __global__ __launch_bounds__(kBlock) void k_fused(KWs ws, KOpts o, const float *
     tile_ctx<TW, TH>(ws, s_views, n_views, t, c);
     float C[3], T;
     int last;
-    tile_forward<B>(ws, o, c, s_rec, s_list, C, T, last, hist);
+    Resident res;
+    tile_forward<B, HIST>(ws, o, c, s_rec, s_idx, s_list, C, T, last, hist, res);
     float g[3] = {0.f, 0.f, 0.f};
     float acc = 0.0f;
     if (c.inside) {
@@ -420,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(KWs ws, KOpts o, const float *
     }
     const float s = block_sum_fixed(acc, s_w);
     if (threadIdx.x == 0) ws.tile_loss[t] = s;
-    tile_backward<B, RED>(ws, o, c, s_rec, s_idx, s_list, s_acc, &s_max, T, last, g, hist);
+    tile_backward<B, RED, HIST>(ws, o, c, s_rec, s_idx, s_list, s_acc, &s_max, T, last, g, hist, res);
   }
 }
 
@@ -496,13 +542,15 @@ int launch_tile_order(const KWs &ws, void *stream) {
     return last_err();                                                      \
   }
 
-// reverse-pass kernels also select the reduction mode
-#define GSR_RED_CALL(KER, TW_, TH_, B_, ...)                                         \
-  do {                                                                             \
-    if (red == 3) hipLaunchKernelGGL((KER<TW_, TH_, B_, 3>), grid, block, 0, s, __VA_ARGS__); \
-    else if (red == 2) hipLaunchKernelGGL((KER<TW_, TH_, B_, 2>), grid, block, 0, s, __VA_ARGS__); \
-    else if (red == 1) hipLaunchKernelGGL((KER<TW_, TH_, B_, 1>), grid, block, 0, s, __VA_ARGS__); \
-    else hipLaunchKernelGGL((KER<TW_, TH_, B_, 0>), grid, block, 0, s, __VA_ARGS__);          \
+// reverse-pass kernels also select the reduction mode; the stored-history
+// variant always takes the row-sum reduction (3)
+#define GSR_RED_CALL(KER, TW_, TH_, B_, ...)                                                           \
+  do {                                                                                               \
+    if (hist) hipLaunchKernelGGL((KER<TW_, TH_, B_, 3, true>), grid, block, 0, s, __VA_ARGS__);      \
+    else if (red == 3) hipLaunchKernelGGL((KER<TW_, TH_, B_, 3, false>), grid, block, 0, s, __VA_ARGS__); \
+    else if (red == 2) hipLaunchKernelGGL((KER<TW_, TH_, B_, 2, false>), grid, block, 0, s, __VA_ARGS__); \
+    else if (red == 1) hipLaunchKernelGGL((KER<TW_, TH_, B_, 1, false>), grid, block, 0, s, __VA_ARGS__); \
+    else hipLaunchKernelGGL((KER<TW_, TH_, B_, 0, false>), grid, block, 0, s, __VA_ARGS__);               \
   } while (0)
 
 int launch_raster_fwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, float *images,
@@ -510,9 +558,15 @@ int launch_raster_fwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t ti
   if (tile_count <= 0) return 0;
   const dim3 grid((unsigned)xcd_grid(tile_count)), block(kBlock);
   hipStream_t s = (hipStream_t)stream;
-#define CALL_FWD(a, b_, B)                                                                                  \
-  hipLaunchKernelGGL((k_raster_fwd<a, b_, B>), grid, block, 0, s, ws, o, tile_lo, tile_count, images, n_views, \
-                     store_history)
+#define CALL_FWD(a, b_, B)                                                                                       \
+  do {                                                                                                             \
+    if (store_history)                                                                                             \
+      hipLaunchKernelGGL((k_raster_fwd<a, b_, B, true>), grid, block, 0, s, ws, o, tile_lo, tile_count, images,    \
+                         n_views);                                                                                 \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_raster_fwd<a, b_, B, false>), grid, block, 0, s, ws, o, tile_lo, tile_count, images,   \
+                         n_views);                                                                                 \
+  } while (0)
   GSR_TILE_DISPATCH(16, 16, CALL_FWD)
   GSR_TILE_DISPATCH(32, 8, CALL_FWD)
   GSR_TILE_DISPATCH(8, 32, CALL_FWD)
@@ -533,8 +587,8 @@ int launch_raster_bwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t ti
   if (tile_count <= 0) return 0;
   const dim3 grid((unsigned)xcd_grid(tile_count)), block(kBlock);
   hipStream_t s = (hipStream_t)stream;
-#define CALL_BWD(a, b_, B) \
-  GSR_RED_CALL(k_raster_bwd, a, b_, B, ws, o, tile_lo, tile_count, dLdC, n_views, use_history)
+  const bool hist = use_history != 0;
+#define CALL_BWD(a, b_, B) GSR_RED_CALL(k_raster_bwd, a, b_, B, ws, o, tile_lo, tile_count, dLdC, n_views)
   GSR_TILE_DISPATCH(16, 16, CALL_BWD)
   GSR_TILE_DISPATCH(32, 8, CALL_BWD)
   GSR_TILE_DISPATCH(8, 32, CALL_BWD)
@@ -547,8 +601,8 @@ int launch_fused(const KWs &ws, const KOpts &o, const float *targets, float *ima
   const dim3 grid((unsigned)grid_blocks), block(kBlock);
   hipStream_t s = (hipStream_t)stream;
   const uint32_t *order = ws.tile_order;
-#define CALL_FUSED(a, b_, B) \
-  GSR_RED_CALL(k_fused, a, b_, B, ws, o, targets, images, n_views, use_history, order)
+  const bool hist = use_history != 0;
+#define CALL_FUSED(a, b_, B) GSR_RED_CALL(k_fused, a, b_, B, ws, o, targets, images, n_views, order)
   GSR_TILE_DISPATCH(16, 16, CALL_FUSED)
   GSR_TILE_DISPATCH(32, 8, CALL_FUSED)
   GSR_TILE_DISPATCH(8, 32, CALL_FUSED)
