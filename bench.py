@@ -236,7 +236,8 @@ def main():
                 amb = fo["ambiguous"][0].astype(bool)
                 err = np.abs(img_g - img_o) / np.maximum(1.0, np.abs(img_o))
                 rel_l2 = float(np.linalg.norm(img_g - img_o) / np.linalg.norm(img_o))
-                g2d = rb.ws_tensor("grad2d", torch.float32, 12 * rb.layout.vn).view(-1, 12)[v * n:(v + 1) * n, :9]
+                S = C.GSR_SLOT_FLOATS
+                g2d = rb.ws_tensor("grad2d", torch.float32, S * rb.layout.vn).view(-1, S)[v * n:(v + 1) * n, :9]
                 g2d = g2d.cpu().numpy().astype(np.float64)
                 go = bo["g2d"].T
                 visv = fo["records"][0]["visible"].astype(bool)

@@ -150,10 +150,14 @@ typedef struct gsr_counts {
   int32_t tile_w, tile_h, bwd_variant, lds_batch, grid_per_cu, mode;
 } gsr_counts;
 
-/* Internal byte offsets of the workspace (for tests and profiling). */
+/* Internal byte offsets of the workspace (for tests and profiling).  grad2d
+ * holds one slot of GSR_SLOT_FLOATS 32-bit words per record: the record's 2D
+ * gradient (dmean 2, dconic 3, dopacity, dcolour 3) in words 0..8, then its
+ * in-tile ranks (4 x u32), tile rectangle (2 x u32) and depth bits. */
+#define GSR_SLOT_FLOATS 16
 typedef struct gsr_layout {
   size_t header, view_table, view_bits, records, grad2d, tile_count, tile_start, tile_fill,
-      tile_loss, tile_order, keys, keys_alt, ranks, pix_T, pix_last, pix_dLdC, history, total;
+      tile_loss, tile_order, keys, keys_alt, pix_T, pix_last, pix_dLdC, history, total;
   int64_t vn;              /* n_views * n record slots (record of (v, i) at v * n + i) */
   int64_t tiles_total;     /* tiles over all views for the plan's tile shape */
   int64_t pixels_total;
@@ -232,10 +236,14 @@ gsr_status gsr_graph_launch(gsr_plan *plan, void *stream);
 gsr_status gsr_query_counts(gsr_plan *plan, const void *ws, gsr_counts *counts, void *stream);
 
 /* Times the batched fused step for each candidate (tile shape 16x16, 32x8,
- * 8x32; lds_batch; grid_per_cu; backward variant within the history budget)
- * with device events and stores the fastest in the plan.  *best receives the
- * choice (fields tile_w/tile_h/bwd_variant/lds_batch/grid_per_cu); best_ms
- * the time of one step (may be NULL). */
+ * 8x32; lds_batch; grid_per_cu; backward variant within the history budget;
+ * reverse reduction 0, 2, 3) with device events, `reps` steps each after one
+ * warm-up step, a candidate scoring its fastest step; the three fastest are
+ * timed again over 2 reps + 3 steps and the fastest of those is stored in
+ * the plan.  Steps write images, loss and grads like
+ * gsr_forward_backward_l1.  *best receives the choice (fields
+ * tile_w/tile_h/bwd_variant/lds_batch/grid_per_cu/bwd_reduce); best_ms the
+ * time of one step (may be NULL). */
 gsr_status gsr_autotune(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams,
                         const float *targets, float *images, float *loss, const gsr_grads *grads,
                         void *ws, size_t ws_bytes, int32_t reps, gsr_options *best,

@@ -70,20 +70,25 @@ struct KGrads {
 //   r3 = rect (x0 | y0 << 16, x1 | y1 << 16), depth (camera z, float bits),
 //        reach of the alpha >= alpha_min ellipse in pixels (float bits)
 constexpr int kRecordFloat4 = 4;
-// 2D gradient of one record: dmean (2), dconic (3), dopacity, dcolour (3), padded to 12 floats.
-constexpr int kGrad2dStride = 12;
+// Slot of one record, 64 bytes (16 x 32 bit, one memory segment):
+//   [0, 9)   2D gradient: dmean (2), dconic (3), dopacity, dcolour (3), summed
+//            by the reverse raster pass (cleared by the projection)
+//   [9, 13)  in-tile ranks of the record's first four tiles (u32)
+//   [13, 15) tile rectangle (x0 | y0 << 16, x1 | y1 << 16)
+//   [15]     depth (camera z, float bits: the sort key's high word)
+// The projection writes the slot whole; the scatter reads its upper half.
+constexpr int kGrad2dStride = GSR_SLOT_FLOATS;
 
 struct KWs {
   WsHeader *hdr;
   ViewInfo *views;
   uint32_t *view_bits;
   float *records;   // [vn][16]
-  float *grad2d;    // [vn][12]
+  float *grad2d;    // [vn][16] record slots
   uint32_t *tile_count, *tile_start, *tile_fill;
   float *tile_loss;
   uint32_t *tile_order;
   uint64_t *keys, *keys_alt;
-  uint32_t *ranks;  // [vn][4]: in-tile rank of a record's first four tiles
   float *pix_T;
   uint32_t *pix_last;
   float *pix_dLdC;

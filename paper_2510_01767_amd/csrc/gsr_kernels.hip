@@ -116,30 +116,32 @@ __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera 
     uint4 r3 = make_uint4((uint32_t)P.x0 | ((uint32_t)P.y0 << 16), (uint32_t)P.x1 | ((uint32_t)P.y1 << 16),
                           __float_as_uint((float)P.tc[2]), __float_as_uint(reach));
     reinterpret_cast<uint4 *>(rec)[3] = r3;
-    float4 *g2 = reinterpret_cast<float4 *>(ws.grad2d + r * kGrad2dStride);
-    g2[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-    g2[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-    g2[2] = make_float4(0.f, 0.f, 0.f, 0.f);
     // Count the record into each tile it touches.  For the first four tiles
     // the count atomic's return value is the record's rank in that tile's
     // bucket, kept so that the scatter needs no atomics; further tiles (large
     // footprints, rare) are counted apart and placed after the ranked ones.
-    uint4 rk = make_uint4(0u, 0u, 0u, 0u);
-    int k = 0;
-    for (int ty = P.y0; ty <= P.y1; ty++)
-      for (int tx = P.x0; tx <= P.x1; tx++, k++) {
-        const int64_t t = vi.tile_base + (int64_t)ty * vi.tiles_x + tx;
-        if (k < 4) {
-          const uint32_t rank = atomicAdd(&ws.tile_count[t], 1u);
-          rk.x = k == 0 ? rank : rk.x;
-          rk.y = k == 1 ? rank : rk.y;
-          rk.z = k == 2 ? rank : rk.z;
-          rk.w = k == 3 ? rank : rk.w;
-        } else {
-          atomicAdd(&ws.tile_fill[t], 1u);
-        }
+    // The first four (row-major) are issued back to back so that their
+    // latencies overlap.
+    const int wx = P.x1 - P.x0 + 1, ntiles = wx * (P.y1 - P.y0 + 1);
+    uint32_t rk[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      if (q < ntiles) {
+        const int dy = q / wx, dx = q - dy * wx;
+        const int64_t t = vi.tile_base + (int64_t)(P.y0 + dy) * vi.tiles_x + (P.x0 + dx);
+        rk[q] = atomicAdd(&ws.tile_count[t], 1u);
       }
-    reinterpret_cast<uint4 *>(ws.ranks)[r] = rk;
+    }
+    for (int q = 4; q < ntiles; q++) {
+      const int dy = q / wx, dx = q - dy * wx;
+      atomicAdd(&ws.tile_fill[vi.tile_base + (int64_t)(P.y0 + dy) * vi.tiles_x + (P.x0 + dx)], 1u);
+    }
+    // the record's slot in one 64-byte write: cleared gradient, ranks, rectangle, depth
+    uint4 *sl = reinterpret_cast<uint4 *>(ws.grad2d + r * kGrad2dStride);
+    sl[0] = make_uint4(0u, 0u, 0u, 0u);
+    sl[1] = make_uint4(0u, 0u, 0u, 0u);
+    sl[2] = make_uint4(0u, rk[0], rk[1], rk[2]);
+    sl[3] = make_uint4(rk[3], r3.x, r3.y, r3.z);
   }
   if (valid) ws.view_bits[i] = bits | fresh;
   if (fresh == 0u) return;
@@ -282,38 +284,170 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(KWs ws, int64_t lo, int64
 // --------------------------------------------------------------------- emit
 
 __global__ __launch_bounds__(kBlock) void k_emit(KWs ws, int64_t n, int n_views, int view_only) {
+  __shared__ ViewInfo s_view[GSR_MAX_VIEWS];
+  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_view[v] = ws.views[v];
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t bits = ws.view_bits[i];
   if (view_only >= 0) bits &= 1u << view_only;
-  while (bits) {
+  for (; bits; bits &= bits - 1) {
     const int v = __ffs(bits) - 1;
-    bits &= bits - 1;
     const int64_t r = (int64_t)v * n + i;
-    const float4 *rec = rec_ptr(ws, r);
-    const uint4 r3 = reinterpret_cast<const uint4 *>(rec)[3];
-    const float depth = __uint_as_float(r3.z);
-    const ViewInfo vi = ws.views[v];
-    const int x0 = r3.x & 0xffff, y0 = r3.x >> 16, x1 = r3.y & 0xffff, y1 = r3.y >> 16;
-    const uint64_t key = ((uint64_t)__float_as_uint(depth) << 32) | (uint64_t)(uint32_t)r;
-    const uint4 rk = reinterpret_cast<const uint4 *>(ws.ranks)[r];
-    int k = 0;
-    for (int ty = y0; ty <= y1; ty++)
-      for (int tx = x0; tx <= x1; tx++, k++) {
-        const int64_t t = vi.tile_base + (int64_t)ty * vi.tiles_x + tx;
-        // ranked entries first, then the overflow entries of large footprints
-        // (tile_fill counted them; counting it back down places them)
-        const uint32_t rank = k == 0 ? rk.x : k == 1 ? rk.y : k == 2 ? rk.z : k == 3 ? rk.w
-                                     : ws.tile_count[t] + atomicSub(&ws.tile_fill[t], 1u) - 1u;
-        const uint64_t slot = (uint64_t)ws.tile_start[t] + rank;
+    const uint4 *sl = reinterpret_cast<const uint4 *>(ws.grad2d + r * kGrad2dStride);
+    const uint4 s2 = sl[2], s3 = sl[3];
+    const ViewInfo &vi = s_view[v];
+    const int x0 = s3.y & 0xffff, y0 = s3.y >> 16, x1 = s3.z & 0xffff;
+    const int wx = x1 - x0 + 1, ntiles = wx * ((int)(s3.z >> 16) - y0 + 1);
+    const uint64_t key = ((uint64_t)s3.w << 32) | (uint64_t)(uint32_t)r;
+    const uint32_t rk[4] = {s2.y, s2.z, s2.w, s3.x};
+    // the ranked first four tiles (row-major), their loads issued together
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      if (q < ntiles) {
+        const int dy = q / wx, dx = q - dy * wx;
+        const int64_t t = vi.tile_base + (int64_t)(y0 + dy) * vi.tiles_x + (x0 + dx);
+        const uint64_t slot = (uint64_t)ws.tile_start[t] + rk[q];
         if (slot < (uint64_t)ws.capacity && slot < (uint64_t)ws.tile_start[t + 1]) ws.keys[slot] = key;
       }
+    }
+    // the overflow entries of large footprints follow the ranked ones
+    // (tile_fill counted them; counting it back down places them)
+    for (int q = 4; q < ntiles; q++) {
+      const int dy = q / wx, dx = q - dy * wx;
+      const int64_t t = vi.tile_base + (int64_t)(y0 + dy) * vi.tiles_x + (x0 + dx);
+      const uint32_t rank = ws.tile_count[t] + atomicSub(&ws.tile_fill[t], 1u) - 1u;
+      const uint64_t slot = (uint64_t)ws.tile_start[t] + rank;
+      if (slot < (uint64_t)ws.capacity && slot < (uint64_t)ws.tile_start[t + 1]) ws.keys[slot] = key;
+    }
   }
 }
 
 // --------------------------------------------------------------------- sort
+// Keys of one tile are unique (the record slot is in the low word), so any
+// correct sort gives the one ascending order.
+//
+// Tiles of at most kWaveSortMax entries: one wavefront per tile, the keys in
+// registers, R per lane, lane-major (element e = lane * R + r in x[r]).  A
+// bitonic network: partners closer than R sit in the same lane, the others
+// in lane ^ (j / R), reached by DPP moves for lane distances 1, 2, 4, 8 and
+// by shuffles for 16 and 32.  No LDS traffic besides those shuffles, no
+// barrier.  Larger tiles: one workgroup per tile, LDS bitonic sort of up to
+// kSortLds keys, merge passes in global memory beyond that.
 
-constexpr int kSortLds = 2048;
+constexpr int kWaveSortMax = 4096;  // 64 lanes x 64 keys
+constexpr int kSortBigThreads = 1024;
+constexpr int kSortLds = 4096;
+
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, 0xf, 0xf, false);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// x from lane ^ m (m a power of two below 64), the whole wavefront active
+template <int M>
+__device__ __forceinline__ uint64_t lane_xor(uint64_t x) {
+  if (M == 1) return dpp_u64<0xB1>(x);                     // quad_perm [1,0,3,2]
+  if (M == 2) return dpp_u64<0x4E>(x);                     // quad_perm [2,3,0,1]
+  if (M == 4) return dpp_u64<0x141>(dpp_u64<0x1B>(x));     // quad_perm [3,2,1,0] then row_half_mirror
+  if (M == 8) return dpp_u64<0x128>(x);                    // row_ror:8
+  return __shfl_xor(x, M);
+}
+
+template <int R, int JS, int KS>
+__device__ __forceinline__ void bitonic_stage(uint64_t (&x)[R], int lane) {
+  constexpr int k = 1 << KS, j = 1 << JS;
+  if (j < R) {
+    // partners in the same lane: e = lane R + r and lane R + (r ^ j)
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      if ((r & j) == 0) {
+        const int q = r | j;
+        const bool up = (((lane * R) | r) & k) == 0;
+        const uint64_t lo = x[r] < x[q] ? x[r] : x[q], hi = x[r] < x[q] ? x[q] : x[r];
+        x[r] = up ? lo : hi;
+        x[q] = up ? hi : lo;
+      }
+    }
+  } else {
+    constexpr int m = j / R;
+    const bool lower = (lane & m) == 0;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const uint64_t y = lane_xor<m>(x[r]);
+      const bool up = (((lane * R) | r) & k) == 0;
+      x[r] = (lower == up) == (x[r] < y) ? x[r] : y;
+    }
+  }
+}
+
+template <int R, int KS, int JS>
+struct BitonicMerge {
+  __device__ __forceinline__ static void run(uint64_t (&x)[R], int lane) {
+    bitonic_stage<R, JS, KS>(x, lane);
+    BitonicMerge<R, KS, JS - 1>::run(x, lane);
+  }
+};
+template <int R, int KS>
+struct BitonicMerge<R, KS, -1> {
+  __device__ __forceinline__ static void run(uint64_t (&)[R], int) {}
+};
+
+template <int R, int KS, int LOGN>
+struct BitonicSort {
+  __device__ __forceinline__ static void run(uint64_t (&x)[R], int lane) {
+    BitonicMerge<R, KS, KS - 1>::run(x, lane);
+    BitonicSort<R, KS + 1, LOGN>::run(x, lane);
+  }
+};
+template <int R, int LOGN>
+struct BitonicSort<R, LOGN + 1, LOGN> {
+  __device__ __forceinline__ static void run(uint64_t (&)[R], int) {}
+};
+
+template <int R>
+__device__ __forceinline__ void wave_sort_tile(uint64_t *keys, int n) {
+  constexpr int kLogN = 6 + (R >= 2) + (R >= 4) + (R >= 8) + (R >= 16) + (R >= 32) + (R >= 64);
+  const int lane = lane_id();
+  uint64_t x[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int e = lane * R + r;
+    x[r] = e < n ? keys[e] : ~0ull;
+  }
+  BitonicSort<R, 1, kLogN>::run(x, lane);
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int e = lane * R + r;
+    if (e < n) keys[e] = x[r];
+  }
+}
+
+// Four tiles per workgroup, one per wavefront (the whole wavefront stays
+// active through the network); tiles of (n_lo, 64 RMAX] entries.  The
+// largest register count is its own kernel, so that the register budget of
+// the common small tiles stays low.
+template <int RMAX>
+__global__ __launch_bounds__(kBlock) void k_sort_wave(KWs ws, int64_t tile_lo, int64_t tile_count, int n_lo) {
+  const int64_t groups = (tile_count + 3) / 4;
+  const int64_t g = xcd_remap(blockIdx.x, groups);
+  if (g >= groups) return;
+  const int64_t b = g * 4 + (threadIdx.x >> 6);
+  if (b >= tile_count) return;
+  const int64_t t = tile_lo + b;
+  const int64_t start = ws.tile_start[t];
+  const int n = (int)((int64_t)ws.tile_start[t + 1] - start);
+  if (n <= 1 || n <= n_lo || n > 64 * RMAX) return;
+  uint64_t *keys = ws.keys + start;
+  if (RMAX >= 32) wave_sort_tile<RMAX>(keys, n);  // n > 1024 here
+  else if (n <= 64) wave_sort_tile<1>(keys, n);
+  else if (n <= 128) wave_sort_tile<2>(keys, n);
+  else if (n <= 256) wave_sort_tile<4>(keys, n);
+  else if (n <= 512) wave_sort_tile<8>(keys, n);
+  else wave_sort_tile<(RMAX >= 16 ? 16 : 8)>(keys, n);
+}
 
 __device__ void bitonic_lds(uint64_t *s, int n2) {
   for (int k = 2; k <= n2; k <<= 1)
@@ -355,15 +489,10 @@ __device__ void merge_runs(const uint64_t *A, int64_t la, const uint64_t *B, int
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sort(KWs ws, int64_t tile_lo, int64_t tile_count) {
-  __shared__ uint64_t s[kSortLds];
-  const int64_t b = xcd_remap(blockIdx.x, tile_count);
-  if (b >= tile_count) return;
-  const int64_t t = tile_lo + b;
+// One workgroup sorts one tile of more than kWaveSortMax entries.
+__device__ void sort_tile_block(const KWs &ws, int64_t t, uint64_t *s) {
   const int64_t start = ws.tile_start[t];
-  const int64_t end = ws.tile_start[t + 1];
-  const int64_t n = end - start;
-  if (n <= 1) return;
+  const int64_t n = (int64_t)ws.tile_start[t + 1] - start;
   uint64_t *keys = ws.keys + start;
   for (int64_t c0 = 0; c0 < n; c0 += kSortLds) {
     const int m = (int)min((int64_t)kSortLds, n - c0);
@@ -374,7 +503,6 @@ __global__ __launch_bounds__(kBlock) void k_sort(KWs ws, int64_t tile_lo, int64_
     for (int k = threadIdx.x; k < m; k += blockDim.x) keys[c0 + k] = s[k];
     __syncthreads();
   }
-  if (n <= kSortLds) return;
   uint64_t *src = keys, *dst = ws.keys_alt + start;
   for (int64_t w = kSortLds; w < n; w <<= 1) {
     for (int64_t a = 0; a < n; a += 2 * w) {
@@ -389,6 +517,30 @@ __global__ __launch_bounds__(kBlock) void k_sort(KWs ws, int64_t tile_lo, int64_
   }
   if (src != keys) {
     for (int64_t k = threadIdx.x; k < n; k += blockDim.x) keys[k] = src[k];
+  }
+  __syncthreads();
+}
+
+// Each workgroup checks kSortBigThreads tiles at once (one per thread),
+// lists the large ones in LDS and sorts them one after the other (the list
+// and its length are uniform per workgroup, so every thread reaches every
+// barrier).  Tiles this large are rare (dense spots of a view).
+__global__ __launch_bounds__(kSortBigThreads) void k_sort_big(KWs ws, int64_t tile_lo, int64_t tile_count) {
+  __shared__ uint64_t s[kSortLds];
+  __shared__ int64_t s_big[kSortBigThreads];
+  __shared__ int s_nbig;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < tile_count; base += (int64_t)gridDim.x * blockDim.x) {
+    if (threadIdx.x == 0) s_nbig = 0;
+    __syncthreads();
+    const int64_t b = base + threadIdx.x;
+    if (b < tile_count) {
+      const int64_t t = tile_lo + b;
+      if ((int64_t)ws.tile_start[t + 1] - ws.tile_start[t] > kWaveSortMax) s_big[atomicAdd(&s_nbig, 1)] = t;
+    }
+    __syncthreads();
+    const int nbig = s_nbig;
+    for (int k = 0; k < nbig; k++) sort_tile_block(ws, s_big[k], s);
+    __syncthreads();
   }
 }
 
@@ -727,8 +879,14 @@ int launch_emit(const KWs &ws, int64_t n, int n_views, int view_only, void *stre
 
 int launch_sort(const KWs &ws, int64_t tile_lo, int64_t tile_count, void *stream) {
   if (tile_count <= 0) return 0;
-  hipLaunchKernelGGL(k_sort, dim3((unsigned)xcd_grid(tile_count)), dim3(kBlock), 0, (hipStream_t)stream, ws,
-                     tile_lo, tile_count);
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 wgrid((unsigned)xcd_grid((tile_count + 3) / 4));
+  hipLaunchKernelGGL(k_sort_wave<16>, wgrid, dim3(kBlock), 0, s, ws, tile_lo, tile_count, 0);
+  hipLaunchKernelGGL(k_sort_wave<32>, wgrid, dim3(kBlock), 0, s, ws, tile_lo, tile_count, 1024);
+  hipLaunchKernelGGL(k_sort_wave<64>, wgrid, dim3(kBlock), 0, s, ws, tile_lo, tile_count, 2048);
+  const int64_t bg = (tile_count + kSortBigThreads - 1) / kSortBigThreads;
+  hipLaunchKernelGGL(k_sort_big, dim3((unsigned)min(bg, (int64_t)4096)), dim3(kSortBigThreads), 0, s, ws, tile_lo,
+                     tile_count);
   return last_err();
 }
 

@@ -23,6 +23,7 @@ GSR_ERR_NONFINITE = 4
 GSR_ERR_HIP = 5
 GSR_ERR_STATE = 6
 GSR_MAX_VIEWS = 32
+GSR_SLOT_FLOATS = 16
 GSR_MODE_PLAIN = 0
 GSR_MODE_BATCHED = 1
 GSR_BWD_AUTO = 0
@@ -74,7 +75,7 @@ class gsr_counts(ctypes.Structure):
 
 class gsr_layout(ctypes.Structure):
     _fields_ = [(k, _sz) for k in ("header", "view_table", "view_bits", "records", "grad2d", "tile_count",
-                                   "tile_start", "tile_fill", "tile_loss", "tile_order", "keys", "keys_alt", "ranks",
+                                   "tile_start", "tile_fill", "tile_loss", "tile_order", "keys", "keys_alt",
                                    "pix_T", "pix_last", "pix_dLdC", "history", "total")] + \
                [(k, _i64) for k in ("vn", "tiles_total", "pixels_total", "capacity", "history_entries")]
 

@@ -97,7 +97,7 @@ def test_layout_and_workspace_size():
     size = C.gsr_workspace_size(plan)
     assert size == L.total
     fields = ["header", "view_table", "view_bits", "records", "grad2d", "tile_count", "tile_start",
-              "tile_fill", "tile_loss", "tile_order", "keys", "keys_alt", "ranks", "pix_T", "pix_last", "pix_dLdC",
+              "tile_fill", "tile_loss", "tile_order", "keys", "keys_alt", "pix_T", "pix_last", "pix_dLdC",
               "history"]
     offs = [getattr(L, f) for f in fields]
     assert all(x % 256 == 0 for x in offs)
@@ -107,6 +107,7 @@ def test_layout_and_workspace_size():
     assert L.tiles_total == 4 * 3 + 3 * 2
     assert L.keys_alt - L.keys >= 8 * 100000
     assert L.records + 64 * L.vn <= L.grad2d
+    assert C.GSR_SLOT_FLOATS == 16 and L.grad2d + 4 * C.GSR_SLOT_FLOATS * L.vn <= L.tile_count
     assert C.gsr_image_offset(plan, 1) == 3 * 64 * 48
     C.gsr_plan_destroy(plan)
     # the stored-history variant reserves capacity * 256 floats within its budget

@@ -1,16 +1,23 @@
 """GPU parity at the benchmark's full sizes.
 
-Config 1 (1M Gaussians, one 1080p view) is checked whole.  Config 2 (3M
-Gaussians, 16 uneven views, the workload bench.py times, in its autotuned
-batched launch) is checked stage by stage on outputs the oracle can compute
-one by one: images and 2D gradients of sampled views, and the reverse
-projection of a seeded 1 % subset of Gaussians fed with the GPU's own 2D
-gradients of every view."""
+Config 1 (1M Gaussians, one 1080p view) is checked whole.  Configs 2 (3M
+Gaussians, 16 uneven views: the workload bench.py times, in its autotuned
+batched launch) and 3 (8M Gaussians, 32 aerial 1080p views) are checked
+stage by stage on outputs the oracle can compute one by one: images, tile
+losses and 2D gradients of sampled views, and the reverse projection and
+densification statistics of a seeded 1 % subset of Gaussians fed with the
+GPU's own 2D gradients of every view.  Config 4 (20M Gaussians, 200+ per
+pixel, 3840x2160) is checked on a window of one view: the oracle renders the
+window through a camera cropped to it (same projection, same tile grid
+phase, the Jacobian clamp scaled to the full frame), pixels, transmittance
+and `last` are compared there, and 2D gradients of the records whose
+footprint lies inside the window."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
+from paper_2510_01767_amd import gsr as C
 from paper_2510_01767_amd import scenes
 from paper_2510_01767_amd.raster import Rasterizer, camera_tensor, pack_images, scene_tensors
 from tests import parity
@@ -64,17 +71,15 @@ def c2():
     return s, r, params, cams, targets
 
 
-def test_config2_sampled_views_match_oracle(c2):
-    s, r, params, cams, targets = c2
+def check_sampled_views(s, r, views):
     o = r.options
     opts = parity.opts_for((o.tile_w, o.tile_h))
     P = oracle.Params.from_scene(s)
     n, V = s.n, s.n_views
     gimgs = parity.gpu_images(r)
     L = r.layout
-    g2d_all = r.ws_tensor("grad2d", torch.float32, 12 * L.vn).view(-1, 12)
+    g2d_all = r.ws_tensor("grad2d", torch.float32, C.GSR_SLOT_FLOATS * L.vn).view(-1, C.GSR_SLOT_FLOATS)
     tile_loss = r.ws_tensor("tile_loss", torch.float32, L.tiles_total).cpu().numpy().astype(np.float64)
-    views = [int(np.argmin([c["W"] * c["H"] for c in s.cameras])), 0]
     tile_base = 0
     bases = []
     for c in s.cameras:
@@ -83,7 +88,7 @@ def test_config2_sampled_views_match_oracle(c2):
     for v in views:
         c = s.cameras[v]
         W, H = c["W"], c["H"]
-        announce("config2 view", v, W, H)
+        announce(s.name, "view", v, W, H)
         fo = oracle.forward(P, [c], opts)
         rep = {}
         parity.compare_images([gimgs[v]], fo, rep)
@@ -119,10 +124,14 @@ def test_config2_sampled_views_match_oracle(c2):
         print("view", v, rep, "grad2d records checked", int(sel.sum()), "kink-excluded", int(kinked.sum()))
 
 
-def test_config2_reverse_projection_on_a_subset(c2):
+def test_config2_sampled_views_match_oracle(c2):
+    s, r, params, cams, targets = c2
+    check_sampled_views(s, r, [int(np.argmin([c["W"] * c["H"] for c in s.cameras])), 0])
+
+
+def check_subset(s, r):
     """Parameter gradients and statistics of a seeded 1 % of the Gaussians:
     the oracle's reverse projection fed with the GPU's 2D gradients."""
-    s, r, params, cams, targets = c2
     n, V = s.n, s.n_views
     rng = np.random.default_rng(20251002)
     sub = np.sort(rng.choice(n, n // 100, replace=False))
@@ -130,7 +139,8 @@ def test_config2_reverse_projection_on_a_subset(c2):
     Ps = oracle.Params(P.means[:, sub].copy(), P.log_scales[:, sub].copy(), P.quats[:, sub].copy(),
                        P.logits[sub].copy(), P.sh[:, sub].copy(), P.sh_degree)
     L = r.layout
-    g2d = r.ws_tensor("grad2d", torch.float32, 12 * L.vn).view(V, n, 12)[:, torch.from_numpy(sub).cuda(), :9]
+    g2d = r.ws_tensor("grad2d", torch.float32, C.GSR_SLOT_FLOATS * L.vn).view(V, n, C.GSR_SLOT_FLOATS)[
+        :, torch.from_numpy(sub).cuda(), :9]
     g2d = g2d.cpu().numpy().astype(np.float64)  # [V][m][9]
     bits = r.ws_tensor("view_bits", torch.int32, n).cpu().numpy().view(np.uint32)[sub]
     opts = parity.opts_for((r.options.tile_w, r.options.tile_h))
@@ -163,3 +173,105 @@ def test_config2_reverse_projection_on_a_subset(c2):
     assert np.all(np.abs(Sg - S)[~excl] <= 1e-3 * (np.abs(S[~excl]) + 1e-2 * rms))
     assert np.array_equal(r.count.cpu().numpy()[sub][~excl], cnt[~excl])
     print("subset", m, rep)
+
+
+def test_config2_reverse_projection_on_a_subset(c2):
+    s, r, params, cams, targets = c2
+    check_subset(s, r)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    s = scenes.config3()
+    announce("config3 scene", s.n, s.n_views)
+    r, params, cams, targets = setup(s, mode="batched")
+    best, ms = r.autotune(params, cams, targets, reps=1)
+    announce("autotuned", best.tile_w, best.tile_h, best.lds_batch, best.grid_per_cu, ms)
+    r.S.zero_()
+    r.count.zero_()
+    r.step_l1(params, cams, targets)
+    torch.cuda.synchronize()
+    return s, r
+
+
+@pytest.mark.timeout(900)
+def test_config3_sampled_views_match_oracle(c3):
+    s, r = c3
+    check_sampled_views(s, r, [0, s.n_views - 1])
+
+
+@pytest.mark.timeout(900)
+def test_config3_reverse_projection_on_a_subset(c3):
+    s, r = c3
+    check_subset(s, r)
+
+
+def window_camera(c, ox, oy, w, h, opts):
+    """Camera cropped to the window [ox, ox + w) x [oy, oy + h) of c, and
+    options with the Jacobian clamp scaled so that its limits (a fraction of
+    the half frame over the focal length) stay those of the full frame."""
+    assert c["W"] * h == c["H"] * w and c["W"] % w == 0
+    wc = dict(c)
+    wc["cx"] = c["cx"] - ox
+    wc["cy"] = c["cy"] - oy
+    wc["W"], wc["H"] = w, h
+    o = oracle.default_opts(tile_w=opts.tile_w, tile_h=opts.tile_h)
+    o.jac_clamp = opts.jac_clamp * (c["W"] // w)
+    return wc, o
+
+
+@pytest.mark.timeout(900)
+def test_config4_window_matches_oracle():
+    s = scenes.config4()
+    announce("config4 scene", s.n, s.n_views)
+    tile = (16, 16)
+    r, params, cams, targets = setup(s, mode="batched", tile=tile, lds_batch=256, grid_per_cu=8)
+    r.step_l1(params, cams, targets, stats=False)
+    torch.cuda.synchronize()
+    counts = r.counts()
+    announce("config4 step", "intersections", counts.intersections_total, "pairs",
+             int(r.ws_tensor("pix_last", torch.int32, r.pixels).sum().item()))
+    v, (ox, oy, w, h) = 0, (1680, 960, 480, 270)
+    c = s.cameras[v]
+    W, H, V, n = c["W"], c["H"], s.n_views, s.n
+    wc, wo = window_camera(c, ox, oy, w, h, parity.opts_for(tile))
+    assert ox % tile[0] == 0 and oy % tile[1] == 0
+    P = oracle.Params.from_scene(s)
+    fo = oracle.forward(P, [wc], wo)
+    img = parity.gpu_images(r)[v][:, oy:oy + h, ox:ox + w]
+    rep = {}
+    parity.compare_images([img], fo, rep)
+    T = r.ws_tensor("pix_T", torch.float32, W * H).cpu().numpy().reshape(H, W)[oy:oy + h, ox:ox + w]
+    last = r.ws_tensor("pix_last", torch.int32, W * H).cpu().numpy().reshape(H, W)[oy:oy + h, ox:ox + w]
+    parity.compare_pixels([T], [last], fo)
+    # 2D gradients of the records whose tiles lie strictly inside the window
+    # (their whole footprint is window pixels), under the full frame's dL/dC
+    t_img = s.targets[v][:, oy:oy + h, ox:ox + w]
+    d = np.sign(fo["images"][0] - t_img) / (3.0 * W * H * V)
+    kink = np.abs(fo["images"][0] - t_img) < parity.L1_KINK
+    bo = oracle.backward(P, [wc], wo, fo, [d])
+    rec = fo["records"][0]
+    gx, gy = fo["grids"][0]
+    x0, y0, x1, y1 = rec["rect"]
+    inner = rec["visible"].astype(bool) & (x0 >= 1) & (y0 >= 1) & (x1 <= gx - 2) & (y1 <= gy - 2)
+    ex = parity.excluded_gaussians(fo, n, wo)
+    kinked = np.zeros(n, bool)
+    if kink.any():
+        ys, xs = np.nonzero(kink.any(axis=0))
+        for t in np.unique((ys // tile[1]) * gx + xs // tile[0]):
+            a_, b_ = fo["bins"]["ranges"][t]
+            kinked[fo["bins"]["values"][a_:b_] % n] = True
+    sel = np.nonzero(inner & ~ex & ~kinked)[0]
+    L = r.layout
+    g2d = r.ws_tensor("grad2d", torch.float32, C.GSR_SLOT_FLOATS * L.vn).view(-1, C.GSR_SLOT_FLOATS)
+    gg = g2d[v * n + torch.from_numpy(sel).cuda(), :9].cpu().numpy().astype(np.float64)
+    go = bo["g2d"].T[sel]
+    assert sel.size > 1000, sel.size
+    for k in range(9):
+        a_, b_ = gg[:, k], go[:, k]
+        rel = np.linalg.norm(a_ - b_) / max(np.linalg.norm(b_), 1e-300)
+        rms = np.sqrt(np.mean(b_ ** 2))
+        assert rel <= 1e-3, (k, rel)
+        assert np.all(np.abs(a_ - b_) <= 1e-3 * (np.abs(b_) + 1e-2 * rms)), k
+    print("config4 window", rep, "records checked", sel.size, "depth complexity",
+          float(fo["last"][0].mean()))
