@@ -5,7 +5,9 @@ Workload (default): 3M-Gaussian SH-3 city block, 16 views of uneven size
 (6 x 1920x1080, 6 x 1600x900, 4 x 960x540), one fused forward + L1 + backward
 step of all views per step, captured in one HIP graph (batched form).  The
 same step is also timed as 16 plain per-view launch chains.  Inputs are
-seeded synthetic data already resident in device memory.
+seeded synthetic data already resident in device memory; the Gaussians are
+stored in Morton order of their means (the layout the framework keeps; the
+generator's random order is timed too, for reference).
 
 Prints one JSON line: Mpixels/s of the batched step (value), Gaussians/s,
 the plain per-view rate and the ratio, the roofline of the dominant kernel
@@ -80,6 +82,9 @@ def main():
     ap.add_argument("--lds-batch", type=int, default=256, help="with --no-autotune")
     ap.add_argument("--grid-per-cu", type=int, default=8, help="with --no-autotune")
     ap.add_argument("--bwd-reduce", type=int, default=3, help="with --no-autotune")
+    ap.add_argument("--order", choices=["morton", "random"], default="morton",
+                    help="storage order of the Gaussians: Morton order of their means (the layout the framework "
+                         "keeps), or the generator's random order")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (a kernel of known traffic, to scale "
                          "hardware byte counters)")
@@ -102,6 +107,9 @@ def main():
     scene = scenes.make_config(args.config)
     log(f"scene {scene.name}: {scene.n} Gaussians, {scene.n_views} views, {scene.pixels} pixels "
         f"({time.time() - t0:.1f} s)")
+    scene_random = scene
+    if args.order == "morton":
+        scene = scene.reordered(scenes.morton_order(scene.means))
     sizes = [(c["W"], c["H"]) for c in scene.cameras]
     params = scene_tensors(scene)
     cams = camera_tensor(scene.cameras)
@@ -179,6 +187,26 @@ def main():
         ms_plain = 1000 * (time.perf_counter() - w0) / args.plain_steps
         log(f"plain per-view step {ms_plain:.3f} ms")
         del rp
+
+    # ---- the same step with the Gaussians in the generator's random order
+    ms_random = None
+    if args.order == "morton" and not args.no_plain:
+        pr = scene_tensors(scene_random)
+        rr = Rasterizer(scene.n, scene.sh_degree, sizes, mode="batched", tile=(opt.tile_w, opt.tile_h),
+                        lds_batch=opt.lds_batch, grid_per_cu=opt.grid_per_cu, bwd_reduce=opt.bwd_reduce)
+        with torch.cuda.stream(stream):
+            rr.capture(pr, cams, targets, stats=False)
+        stream.synchronize()
+        for _ in range(args.warmup):
+            rr.launch(stream=stream)
+        e0.record(stream)
+        for _ in range(args.steps):
+            rr.launch(stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_random = e0.elapsed_time(e1) / args.steps
+        log(f"random-order graph step {ms_random:.3f} ms")
+        del rr, pr
 
     # ---- algorithmic work of the dominant kernel
     n, V = scene.n, scene.n_views
@@ -271,15 +299,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": scene.name, "gaussians": n, "views": V, "pixels": P,
+        "config": {"workload": scene_random.name, "gaussians": n, "views": V, "pixels": P,
                    "form": "batched fused fwd+L1+bwd, one HIP graph",
                    "tile": f"{opt.tile_w}x{opt.tile_h}", "lds_batch": opt.lds_batch,
-                   "grid_per_cu": opt.grid_per_cu, "bwd_variant": "stored" if counts.bwd_variant == 2 else "recompute"},
+                   "grid_per_cu": opt.grid_per_cu, "bwd_variant": "stored" if counts.bwd_variant == 2 else "recompute",
+                   "gaussian_order": args.order},
         "gaussians_per_s": round(n * V / (ms_batched * 1e-3), 1),
         "visible_gaussian_views_per_s": round(vis / (ms_batched * 1e-3), 1),
         "plain_ms_per_step": None if ms_plain is None else round(ms_plain, 3),
         "plain_mpixels_per_s": None if ms_plain is None else round(P / (ms_plain * 1e-3) / 1e6, 2),
         "batched_vs_plain": None if ms_plain is None else round(ms_plain / ms_batched, 3),
+        "random_order_ms_per_step": None if ms_random is None else round(ms_random, 4),
         "loss": loss_gpu,
         "counts": {"visible": vis, "union": counts.visible_union, "intersections": I, "pairs": pairs},
         "roofline": roof,

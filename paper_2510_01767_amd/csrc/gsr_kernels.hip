@@ -96,52 +96,88 @@ __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera 
   const float pmin = c2 > 0.0 ? (float)(-0.5 * c2) : 0.0f;
   uint32_t bits = (valid && or_bits) ? ws.view_bits[i] : 0u;
   uint32_t fresh = 0u;  // views found visible by this call
+  const int lane = lane_id();
+  const uint64_t below = (1ull << lane) - 1ull;
   for (int v = view_lo; v < view_hi; v++) {
     const ViewInfo &vi = s_view[v];
     const Cam64 &cam = s_cam[v];
     Proj P;
     // the exact projection only where the conservative bound leaves a chance
     const bool vis = keep && maybe_visible(g, cam, o) && project_view(g, cam, o, P);
-    if (!vis) continue;
-    fresh |= 1u << v;
+    if (__ballot(vis) == 0ull) continue;  // (the whole wavefront stays in the loop)
     const int64_t r = (int64_t)v * n + i;
-    float4 *rec = reinterpret_cast<float4 *>(ws.records) + r * kRecordFloat4;
-    const float mxh = (float)P.mx, myh = (float)P.my;
-    rec[0] = make_float4(mxh, myh, (float)(P.mx - (double)mxh), (float)(P.my - (double)myh));
-    rec[1] = make_float4((float)P.A, (float)P.B, (float)P.C, (float)g.opac);
-    // the reach gets a relative and an absolute pad, so no pixel that the
-    // float32 alpha test accepts lies outside it; -1 when even the centre
-    // cannot reach alpha_min
-    const float reach = c2 > 0.0 ? (float)(sqrt(c2 * P.lam) * 1.001 + 0.01) : -1.0f;
-    uint4 r3 = make_uint4((uint32_t)P.x0 | ((uint32_t)P.y0 << 16), (uint32_t)P.x1 | ((uint32_t)P.y1 << 16),
-                          __float_as_uint((float)P.tc[2]), __float_as_uint(reach));
-    reinterpret_cast<uint4 *>(rec)[3] = r3;
+    uint4 r3 = make_uint4(0u, 0u, 0u, 0u);
+    int wx = 1, ntiles = 0;
+    if (vis) {
+      fresh |= 1u << v;
+      float4 *rec = reinterpret_cast<float4 *>(ws.records) + r * kRecordFloat4;
+      const float mxh = (float)P.mx, myh = (float)P.my;
+      rec[0] = make_float4(mxh, myh, (float)(P.mx - (double)mxh), (float)(P.my - (double)myh));
+      rec[1] = make_float4((float)P.A, (float)P.B, (float)P.C, (float)g.opac);
+      // the reach gets a relative and an absolute pad, so no pixel that the
+      // float32 alpha test accepts lies outside it; -1 when even the centre
+      // cannot reach alpha_min
+      const float reach = c2 > 0.0 ? (float)(sqrt(c2 * P.lam) * 1.001 + 0.01) : -1.0f;
+      r3 = make_uint4((uint32_t)P.x0 | ((uint32_t)P.y0 << 16), (uint32_t)P.x1 | ((uint32_t)P.y1 << 16),
+                      __float_as_uint((float)P.tc[2]), __float_as_uint(reach));
+      reinterpret_cast<uint4 *>(rec)[3] = r3;
+      wx = P.x1 - P.x0 + 1;
+      ntiles = wx * (P.y1 - P.y0 + 1);
+    }
     // Count the record into each tile it touches.  For the first four tiles
-    // the count atomic's return value is the record's rank in that tile's
-    // bucket, kept so that the scatter needs no atomics; further tiles (large
-    // footprints, rare) are counted apart and placed after the ranked ones.
-    // The first four (row-major) are issued back to back so that their
-    // latencies overlap.
-    const int wx = P.x1 - P.x0 + 1, ntiles = wx * (P.y1 - P.y0 + 1);
+    // (row-major) the count atomic's return value is the record's rank in
+    // that tile's bucket, kept so that the scatter needs no atomics; further
+    // tiles (large footprints, rare) are counted apart and placed after the
+    // ranked ones.  When the wavefront's records sit close together on the
+    // tile grid (Gaussians stored in spatial order), lanes that share a tile
+    // take one atomic for all of them, ranked by lane within it; otherwise,
+    // and for what a few rounds leave, one atomic per (record, tile).
+    const int x0 = P.x0, y0 = P.y0;
+    auto tile_q = [&](int q) -> int32_t {
+      const int dy = q / wx, dx = q - dy * wx;
+      return (int32_t)(vi.tile_base + (int64_t)(y0 + dy) * vi.tiles_x + (x0 + dx));
+    };
+    const int32_t t0 = vis ? tile_q(0) : 0;
+    int32_t tmin = vis ? t0 : INT32_MAX, tmax = vis ? t0 : -1;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+      tmin = min(tmin, __shfl_xor(tmin, m));
+      tmax = max(tmax, __shfl_xor(tmax, m));
+    }
+    const bool gather = tmax - tmin <= 2 * vi.tiles_x + 2;
     uint32_t rk[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-      if (q < ntiles) {
-        const int dy = q / wx, dx = q - dy * wx;
-        const int64_t t = vi.tile_base + (int64_t)(P.y0 + dy) * vi.tiles_x + (P.x0 + dx);
-        rk[q] = atomicAdd(&ws.tile_count[t], 1u);
+      const int32_t t = q < ntiles ? tile_q(q) : -1;
+      bool pending = t >= 0;
+      if (gather) {
+        for (int round = 0; round < 8; round++) {
+          const uint64_t act = __ballot(pending);
+          if (act == 0ull) break;
+          const int leader = __ffsll((unsigned long long)act) - 1;
+          const int32_t lt = __shfl(t, leader);
+          const bool same = pending && t == lt;
+          const uint64_t m = __ballot(same);
+          uint32_t base = 0u;
+          if (lane == leader) base = atomicAdd(&ws.tile_count[lt], (uint32_t)__popcll(m));
+          base = __shfl(base, leader);
+          if (same) {
+            rk[q] = base + (uint32_t)__popcll(m & below);
+            pending = false;
+          }
+        }
       }
+      if (pending) rk[q] = atomicAdd(&ws.tile_count[t], 1u);
     }
-    for (int q = 4; q < ntiles; q++) {
-      const int dy = q / wx, dx = q - dy * wx;
-      atomicAdd(&ws.tile_fill[vi.tile_base + (int64_t)(P.y0 + dy) * vi.tiles_x + (P.x0 + dx)], 1u);
+    for (int q = 4; q < ntiles; q++) atomicAdd(&ws.tile_fill[tile_q(q)], 1u);
+    if (vis) {
+      // the record's slot in one 64-byte write: cleared gradient, ranks, rectangle, depth
+      uint4 *sl = reinterpret_cast<uint4 *>(ws.grad2d + r * kGrad2dStride);
+      sl[0] = make_uint4(0u, 0u, 0u, 0u);
+      sl[1] = make_uint4(0u, 0u, 0u, 0u);
+      sl[2] = make_uint4(0u, rk[0], rk[1], rk[2]);
+      sl[3] = make_uint4(rk[3], r3.x, r3.y, r3.z);
     }
-    // the record's slot in one 64-byte write: cleared gradient, ranks, rectangle, depth
-    uint4 *sl = reinterpret_cast<uint4 *>(ws.grad2d + r * kGrad2dStride);
-    sl[0] = make_uint4(0u, 0u, 0u, 0u);
-    sl[1] = make_uint4(0u, 0u, 0u, 0u);
-    sl[2] = make_uint4(0u, rk[0], rk[1], rk[2]);
-    sl[3] = make_uint4(rk[3], r3.x, r3.y, r3.z);
   }
   if (valid) ws.view_bits[i] = bits | fresh;
   if (fresh == 0u) return;

@@ -60,6 +60,30 @@ class Scene:
     def pixels(self) -> int:
         return int(sum(c["W"] * c["H"] for c in self.cameras))
 
+    def reordered(self, perm: np.ndarray) -> "Scene":
+        """The same scene with its Gaussians stored in the order `perm`."""
+        c = lambda a: np.ascontiguousarray(a[..., perm])
+        return dataclasses.replace(self, means=c(self.means), log_scales=c(self.log_scales), quats=c(self.quats),
+                                   opacity_logits=c(self.opacity_logits), sh=c(self.sh),
+                                   name=self.name + "-reordered", info=dict(self.info, order="permuted"))
+
+
+def morton_order(means: np.ndarray, bits: int = 10) -> np.ndarray:
+    """Permutation sorting Gaussians by the Morton (Z-order) code of their
+    means, quantised to 2^bits cells per axis of their bounding box (stable
+    for equal codes).  Stored in this order, the Gaussians of one wavefront
+    are spatial neighbours: they see the same views and touch the same tiles.
+    Nothing the rasterizer computes depends on the order."""
+    m = np.asarray(means, np.float64)
+    lo = m.min(axis=1, keepdims=True)
+    span = np.maximum(m.max(axis=1, keepdims=True) - lo, 1e-30)
+    q = np.minimum((m - lo) / span * (1 << bits), (1 << bits) - 1).astype(np.uint64)
+    code = np.zeros(m.shape[1], np.uint64)
+    for b in range(bits):
+        for a in range(3):
+            code |= ((q[a] >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + a)
+    return np.argsort(code, kind="stable")
+
 
 # --------------------------------------------------------------------------
 # cameras
