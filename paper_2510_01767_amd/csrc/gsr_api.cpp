@@ -94,7 +94,8 @@ void compute_layout(gsr_plan &p) {
   take(L.tile_start, sizeof(uint32_t) * (size_t)(tmax + 1));
   take(L.tile_fill, sizeof(uint32_t) * (size_t)tmax);
   take(L.tile_loss, sizeof(float) * (size_t)tmax);
-  take(L.tile_order, sizeof(uint32_t) * (size_t)tmax);
+  // the schedule order; before the sort, the scan's chunk sums (8 bytes per 4096 tiles)
+  take(L.tile_order, std::max(sizeof(uint32_t) * (size_t)tmax, sizeof(uint64_t) * (size_t)(tmax / 4096 + 2)));
   take(L.keys, sizeof(uint64_t) * (size_t)L.capacity);
   take(L.keys_alt, sizeof(uint64_t) * (size_t)L.capacity);
   take(L.pix_T, sizeof(float) * (size_t)L.pixels_total);

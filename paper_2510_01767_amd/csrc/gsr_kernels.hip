@@ -258,54 +258,88 @@ __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
   return x;
 }
 
-// Chunks of 4 * 1024 consecutive counts: each thread scans 4 in registers,
-// wavefronts scan thread sums with shuffles, the 16 wavefront sums are
-// scanned by wavefront 0, and a carry walks from chunk to chunk.  View start
-// offsets are recorded on the way (unclamped), giving per-view counts.
-__global__ __launch_bounds__(kScanThreads) void k_scan(KWs ws, int64_t lo, int64_t hi, int64_t base,
-                                                        int view_lo, int view_hi) {
+// Three passes over chunks of kScanChunk consecutive tiles (counts plus
+// overflow counts): the sum of every chunk, then one workgroup scans the chunk
+// sums and finds where each view starts, then every chunk scans itself from
+// its prefix.  The chunk sums live in the tile-order array, which is written
+// only after the sort.  No workgroup waits on another.
+constexpr int kScanChunk = 4 * kScanThreads;
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) x += __shfl_xor(x, m);
+  return x;
+}
+
+// Sum over the workgroup (kScanThreads threads); every thread gets it.
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t x, uint64_t *s_w) {
+  constexpr int kWaves = kScanThreads / 64;
+  x = wave_sum_u64(x);
+  __syncthreads();
+  if (lane_id() == 0) s_w[threadIdx.x >> 6] = x;
+  __syncthreads();
+  uint64_t t = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; w++) t += s_w[w];
+  return t;
+}
+
+__device__ __forceinline__ uint32_t tile_total(const KWs &ws, int64_t t, int64_t hi) {
+  return t < hi ? ws.tile_count[t] + ws.tile_fill[t] : 0u;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(KWs ws, int64_t lo, int64_t hi) {
+  __shared__ uint64_t s_w[kScanThreads / 64];
+  const int64_t t0 = lo + (int64_t)blockIdx.x * kScanChunk + 4 * (int64_t)threadIdx.x;
+  uint64_t x = 0;
+#pragma unroll
+  for (int q = 0; q < 4; q++) x += tile_total(ws, t0 + q, hi);
+  const uint64_t sum = block_sum_u64(x, s_w);
+  if (threadIdx.x == 0) reinterpret_cast<uint64_t *>(ws.tile_order)[blockIdx.x] = sum;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_chunks(KWs ws, int64_t lo, int64_t hi, int64_t base,
+                                                               int view_lo, int view_hi, int nchunks) {
   constexpr int kWaves = kScanThreads / 64;
   __shared__ uint64_t s_wave[kWaves];
-  __shared__ uint64_t s_carry;
-  __shared__ uint64_t s_vstart[GSR_MAX_VIEWS + 1];
-  __shared__ int64_t s_vbase[GSR_MAX_VIEWS];
+  __shared__ uint64_t s_w[kWaves];
+  __shared__ uint64_t s_vstart[GSR_MAX_VIEWS];
+  uint64_t *sums = reinterpret_cast<uint64_t *>(ws.tile_order);
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  // exclusive scan of the chunk sums (at most kScanChunk chunks), plus base
+  uint64_t x[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) x[q] = 4 * tid + q < nchunks ? sums[4 * tid + q] : 0ull;
+  const uint64_t s = x[0] + x[1] + x[2] + x[3];
+  const uint64_t incl = wave_incl_scan(s);
+  if (lane == 63) s_wave[wave] = incl;
+  __syncthreads();
+  uint64_t before = 0;
+  for (int w = 0; w < wave; w++) before += s_wave[w];
+  uint64_t pre = (uint64_t)base + before + (incl - s);
+  uint64_t total = (uint64_t)base;
+  for (int w = 0; w < kWaves; w++) total += s_wave[w];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    if (4 * tid + q < nchunks) sums[4 * tid + q] = pre;
+    pre += x[q];
+  }
+  __syncthreads();
+  // where each view's first tile starts: its chunk's prefix plus the counts
+  // in front of it within the chunk
   const int nv = view_hi - view_lo;
-  if (tid < nv) s_vbase[tid] = ws.views[view_lo + tid].tile_base;
-  if (tid == 0) s_carry = (uint64_t)base;
+  for (int v = 0; v < nv; v++) {
+    const int64_t tb = ws.views[view_lo + v].tile_base;
+    const int64_t c = (tb - lo) / kScanChunk;
+    const int64_t c0 = lo + c * kScanChunk;
+    uint64_t part = 0;
+    for (int64_t t = c0 + tid; t < tb; t += kScanThreads) part += tile_total(ws, t, hi);
+    part = block_sum_u64(part, s_w);
+    if (tid == 0) s_vstart[v] = sums[c] + part;
+  }
   __syncthreads();
   const uint64_t cap = (uint64_t)ws.capacity;
-  for (int64_t c0 = lo; c0 < hi; c0 += 4 * kScanThreads) {
-    const int64_t t0 = c0 + 4 * (int64_t)tid;
-    uint32_t x[4];
-#pragma unroll
-    for (int q = 0; q < 4; q++) x[q] = t0 + q < hi ? ws.tile_count[t0 + q] + ws.tile_fill[t0 + q] : 0u;
-    const uint64_t s = (uint64_t)x[0] + x[1] + x[2] + x[3];
-    const uint64_t incl = wave_incl_scan(s);
-    if (lane == 63) s_wave[wave] = incl;
-    __syncthreads();
-    if (wave == 0) {
-      const uint64_t w = lane < kWaves ? s_wave[lane] : 0ull;
-      const uint64_t wi = wave_incl_scan(w);
-      if (lane < kWaves) s_wave[lane] = wi - w;  // exclusive
-    }
-    __syncthreads();
-    uint64_t pre = s_carry + s_wave[wave] + (incl - s);
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      const int64_t t = t0 + q;
-      if (t < hi) {
-        ws.tile_start[t] = (uint32_t)min(pre, cap);
-        for (int v = 0; v < nv; v++)
-          if (s_vbase[v] == t) s_vstart[v] = pre;
-      }
-      pre += x[q];
-    }
-    __syncthreads();
-    if (tid == kScanThreads - 1) s_carry = pre;
-    __syncthreads();
-  }
-  const uint64_t total = s_carry;  // base + all counts
   if (tid == 0) {
     ws.tile_start[hi] = (uint32_t)min(total, cap);
     if (total > cap) ws.hdr->overflow = 1u;
@@ -314,6 +348,29 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(KWs ws, int64_t lo, int64
   if (tid < nv) {
     const uint64_t a = s_vstart[tid], b = tid + 1 < nv ? s_vstart[tid + 1] : total;
     ws.hdr->isect[view_lo + tid] = (uint32_t)min(b - a, (uint64_t)0xffffffffu);
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(KWs ws, int64_t lo, int64_t hi) {
+  constexpr int kWaves = kScanThreads / 64;
+  __shared__ uint64_t s_wave[kWaves];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const int64_t t0 = lo + (int64_t)blockIdx.x * kScanChunk + 4 * (int64_t)tid;
+  uint32_t x[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) x[q] = tile_total(ws, t0 + q, hi);
+  const uint64_t s = (uint64_t)x[0] + x[1] + x[2] + x[3];
+  const uint64_t incl = wave_incl_scan(s);
+  if (lane == 63) s_wave[wave] = incl;
+  __syncthreads();
+  uint64_t before = 0;
+  for (int w = 0; w < wave; w++) before += s_wave[w];
+  uint64_t pre = reinterpret_cast<const uint64_t *>(ws.tile_order)[blockIdx.x] + before + (incl - s);
+  const uint64_t cap = (uint64_t)ws.capacity;
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    if (t0 + q < hi) ws.tile_start[t0 + q] = (uint32_t)min(pre, cap);
+    pre += x[q];
   }
 }
 
@@ -582,22 +639,25 @@ __global__ __launch_bounds__(kSortBigThreads) void k_sort_big(KWs ws, int64_t ti
 
 // --------------------------------------------------------------- loss total
 
-__global__ __launch_bounds__(kBlock) void k_loss(KWs ws, int n_views, float *loss) {
-  __shared__ double s_acc[kBlock];
+// Deterministic: fixed thread mapping and reduction tree, double accumulation.
+__global__ __launch_bounds__(kScanThreads) void k_loss(KWs ws, int n_views, float *loss) {
+  constexpr int kWaves = kScanThreads / 64;
+  __shared__ double s_w[kWaves];
   double total = 0.0;
   for (int v = 0; v < n_views; v++) {
     const ViewInfo vi = ws.views[v];
     const int64_t nt = (int64_t)vi.tiles_x * vi.tiles_y;
     double a = 0.0;
-    for (int64_t k = threadIdx.x; k < nt; k += blockDim.x) a += (double)ws.tile_loss[vi.tile_base + k];
-    s_acc[threadIdx.x] = a;
+    for (int64_t k = threadIdx.x; k < nt; k += kScanThreads) a += (double)ws.tile_loss[vi.tile_base + k];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) a += __shfl_xor(a, m);
     __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-      if (threadIdx.x < off) s_acc[threadIdx.x] += s_acc[threadIdx.x + off];
-      __syncthreads();
-    }
-    total += s_acc[0] * (double)vi.loss_scale;
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = a;
     __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) t += s_w[w];
+    total += t * (double)vi.loss_scale;
   }
   if (threadIdx.x == 0) *loss = (float)total;
 }
@@ -903,8 +963,16 @@ int launch_project(const KParams &p, const gsr_camera *cams, const KOpts &o, con
 }
 
 int launch_scan(const KWs &ws, int64_t lo, int64_t hi, int64_t base, int view_lo, int view_hi, void *stream) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, (hipStream_t)stream, ws, lo, hi, base, view_lo,
-                     view_hi);
+  if (hi <= lo) return (int)hipErrorInvalidValue;
+  const int64_t nchunks = (hi - lo + kScanChunk - 1) / kScanChunk;
+  // chunk sums in the tile-order array (sized for 8 bytes per chunk of the
+  // largest tile grid); one workgroup scans at most kScanChunk of them
+  if (nchunks > kScanChunk) return (int)hipErrorInvalidValue;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nchunks), dim3(kScanThreads), 0, s, ws, lo, hi);
+  hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(kScanThreads), 0, s, ws, lo, hi, base, view_lo, view_hi,
+                     (int)nchunks);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nchunks), dim3(kScanThreads), 0, s, ws, lo, hi);
   return last_err();
 }
 
@@ -940,7 +1008,7 @@ int launch_project_bwd(const KParams &p, const gsr_camera *cams, const KOpts &o,
 }
 
 int launch_loss(const KWs &ws, int n_views, float *loss, void *stream) {
-  hipLaunchKernelGGL(k_loss, dim3(1), dim3(kBlock), 0, (hipStream_t)stream, ws, n_views, loss);
+  hipLaunchKernelGGL(k_loss, dim3(1), dim3(kScanThreads), 0, (hipStream_t)stream, ws, n_views, loss);
   return last_err();
 }
 
