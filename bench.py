@@ -78,6 +78,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-adam", action="store_true")
     ap.add_argument("--tile", default=None, help="fixed tile shape WxH (with --no-autotune)")
     ap.add_argument("--lds-batch", type=int, default=256, help="with --no-autotune")
     ap.add_argument("--grid-per-cu", type=int, default=8, help="with --no-autotune")
@@ -108,6 +109,7 @@ def main():
     log(f"scene {scene.name}: {scene.n} Gaussians, {scene.n_views} views, {scene.pixels} pixels "
         f"({time.time() - t0:.1f} s)")
     scene_random = scene
+    n_total = scene.n
     if args.order == "morton":
         scene = scene.reordered(scenes.morton_order(scene.means))
     sizes = [(c["W"], c["H"]) for c in scene.cameras]
@@ -207,6 +209,38 @@ def main():
         ms_random = e0.elapsed_time(e1) / args.steps
         log(f"random-order graph step {ms_random:.3f} ms")
         del rr, pr
+
+    # ---- the optimizer stage after the step: Adam over all parameter planes, dense and
+    # visible-only (the step's view masks), on copies of the parameters
+    adam = None
+    if not args.no_adam:
+        from paper_2510_01767_amd.raster import PARAM_NAMES
+        pa = {k: params[k].clone() for k in PARAM_NAMES}
+        ma = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+        va = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+        lr = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3, 1.25e-4)
+        rb.step_l1(params, cams, targets, stats=False, stream=stream)
+        res = {}
+        for name, vis in (("dense", False), ("visible_only", True)):
+            rb.adam_step(pa, rb.grads, ma, va, lr, 1, visible_only=vis, stream=stream)
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record(stream)
+            for t in range(args.steps):
+                rb.adam_step(pa, rb.grads, ma, va, lr, t + 2, visible_only=vis, stream=stream)
+            a1.record(stream)
+            torch.cuda.synchronize()
+            res[name] = a0.elapsed_time(a1) / args.steps
+        planes = 11 + 3 * (scene.sh_degree + 1) ** 2
+        b_dense = 7 * 4 * planes * n_total
+        b_vis = 7 * 4 * planes * counts.visible_union + 4 * n_total * planes
+        gbs = b_dense / (res["dense"] * 1e-3) / 1e9
+        adam = {"dense_ms": round(res["dense"], 4), "visible_only_ms": round(res["visible_only"], 4),
+                "bytes_dense": b_dense, "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                                                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)},
+                "visible_fraction": round(counts.visible_union / n_total, 4),
+                "visible_only_GBps": round(b_vis / (res["visible_only"] * 1e-3) / 1e9, 1)}
+        log(f"adam: {adam}")
+        del pa, ma, va
 
     # ---- algorithmic work of the dominant kernel
     n, V = scene.n, scene.n_views
@@ -313,6 +347,7 @@ def main():
         "loss": loss_gpu,
         "counts": {"visible": vis, "union": counts.visible_union, "intersections": I, "pairs": pairs},
         "roofline": roof,
+        "adam": adam,
         "parity": parity,
         "cpu_baseline": cpu,
     }

@@ -268,6 +268,28 @@ gsr_status gsr_plan_options(const gsr_plan *plan, gsr_options *opt);
  * grid_per_cu) of a plan; drops a captured graph. */
 gsr_status gsr_plan_set_tuning(gsr_plan *plan, const gsr_options *opt);
 
+/* ---- Optimizer step (the NEXT stage after the reverse projection) ------
+ * The paper locates the cost of Gaussians that no assigned camera sees in the
+ * optimizer rather than in rendering (Sec. 3.3) and uses Sparse Adam in the
+ * coarse stage (App. A.1).  One Adam step (Kingma & Ba, bias-corrected) over
+ * every parameter plane of the plan's n Gaussians:
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   p -= lr / (1 - b1^t) * m / (sqrt(v) / sqrt(1 - b2^t) + eps)
+ * with one learning rate per group.  params, grads, m, v: device planes in
+ * the gsr_gaussians layout (grads as written by the reverse pass); updated in
+ * place.  visible_bits: NULL for the dense step, else [n] u32 (e.g. the
+ * workspace's view_bits of the last step): Gaussians whose word is 0 keep
+ * their parameters and moments untouched (visible-only Adam).  float32
+ * arithmetic; bias corrections in float64 on the host. */
+typedef struct gsr_adam {
+  float lr[6];  /* means, log_scales, quats, opacity_logits, SH band 0, SH bands >= 1 */
+  float beta1, beta2, eps;
+  int32_t step; /* t >= 1 */
+} gsr_adam;
+
+gsr_status gsr_adam_step(gsr_plan *plan, const gsr_adam *hp, const gsr_grads *params, const gsr_grads *grads,
+                         const gsr_grads *m, const gsr_grads *v, const uint32_t *visible_bits, void *stream);
+
 const char *gsr_status_string(gsr_status s);
 const char *gsr_last_error(const gsr_plan *plan);
 

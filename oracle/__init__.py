@@ -393,3 +393,44 @@ def visibility_mask(P: Params, cams: list, opts: Opts, aabb, keep=None):
     aabb = np.asarray(aabb, np.float64)
     inb = np.all((P.means >= aabb[:3, None]) & (P.means < aabb[3:, None]), axis=0)
     return bits, (bits != 0).astype(np.uint8), inb.astype(np.uint8)
+
+
+ADAM_GROUPS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+def adam_step(params: dict, grads: dict, m: dict, v: dict, lr, beta1: float, beta2: float, eps: float,
+              step: int, visible=None):
+    """One bias-corrected Adam step (Kingma & Ba, Alg. 1) on every parameter
+    plane, the optimizer whose cost visibility cropping removes for unseen
+    Gaussians (Sec. 3.3; Sparse Adam, App. A.1).  Written from the
+    definition, in float64 on copies:
+
+        m_t = b1 m_{t-1} + (1 - b1) g,   v_t = b2 v_{t-1} + (1 - b2) g^2,
+        m^ = m_t / (1 - b1^t),           v^ = v_t / (1 - b2^t),
+        p_t = p_{t-1} - lr m^ / (sqrt(v^) + eps)
+
+    lr: six rates (means, log_scales, quats, opacity_logits, SH band 0 = the
+    first three SH planes, the other SH planes).  visible: None (dense) or a
+    [n] array; Gaussians with visible == 0 keep parameters and moments.
+    Returns new (params, m, v) dicts of float64 arrays [rows][n]."""
+    P, M, V = {}, {}, {}
+    for k in ADAM_GROUPS:
+        p = np.asarray(params[k], np.float64).reshape(-1, np.asarray(params[k]).shape[-1]).copy()
+        g = np.asarray(grads[k], np.float64).reshape(p.shape)
+        mk = np.asarray(m[k], np.float64).reshape(p.shape).copy()
+        vk = np.asarray(v[k], np.float64).reshape(p.shape).copy()
+        if k == "sh":
+            rate = np.full((p.shape[0], 1), float(lr[5]))
+            rate[:3] = float(lr[4])
+        else:
+            rate = np.full((p.shape[0], 1), float(lr[ADAM_GROUPS.index(k)]))
+        upd = np.ones(p.shape[1], bool) if visible is None else (np.asarray(visible) != 0)
+        m_new = beta1 * mk + (1.0 - beta1) * g
+        v_new = beta2 * vk + (1.0 - beta2) * g * g
+        m_hat = m_new / (1.0 - beta1 ** step)
+        v_hat = v_new / (1.0 - beta2 ** step)
+        p_new = p - rate * m_hat / (np.sqrt(v_hat) + eps)
+        P[k] = np.where(upd, p_new, p)
+        M[k] = np.where(upd, m_new, mk)
+        V[k] = np.where(upd, v_new, vk)
+    return P, M, V

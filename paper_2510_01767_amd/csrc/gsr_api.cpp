@@ -787,6 +787,44 @@ gsr_status gsr_autotune(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera
   return GSR_OK;
 }
 
+gsr_status gsr_adam_step(gsr_plan *plan, const gsr_adam *hp, const gsr_grads *params, const gsr_grads *grads,
+                         const gsr_grads *m, const gsr_grads *v, const uint32_t *visible_bits, void *stream) {
+  if (!plan) return GSR_ERR_INVALID_ARG;
+  if (!hp || check_grads(params) != GSR_OK || check_grads(grads) != GSR_OK || check_grads(m) != GSR_OK ||
+      check_grads(v) != GSR_OK)
+    return fail(plan, GSR_ERR_INVALID_ARG, "null argument");
+  if (hp->step < 1) return fail(plan, GSR_ERR_INVALID_ARG, "step must be >= 1");
+  if (!(hp->beta1 >= 0.0f && hp->beta1 < 1.0f && hp->beta2 >= 0.0f && hp->beta2 < 1.0f && hp->eps > 0.0f))
+    return fail(plan, GSR_ERR_INVALID_ARG, "need 0 <= beta1, beta2 < 1 and eps > 0");
+  for (int k = 0; k < 6; k++)
+    if (!std::isfinite(hp->lr[k])) return fail(plan, GSR_ERR_INVALID_ARG, "learning rates must be finite");
+  const int K = (plan->prob.sh_degree + 1) * (plan->prob.sh_degree + 1);
+  KAdam a;
+  float *const ps[5] = {params->means, params->log_scales, params->quats, params->opacity_logits, params->sh};
+  const float *const gs[5] = {grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->sh};
+  float *const ms[5] = {m->means, m->log_scales, m->quats, m->opacity_logits, m->sh};
+  float *const vs[5] = {v->means, v->log_scales, v->quats, v->opacity_logits, v->sh};
+  const int rows[5] = {3, 3, 4, 1, 3 * K};
+  for (int k = 0; k < 5; k++) {
+    a.p[k] = ps[k];
+    a.g[k] = gs[k];
+    a.m[k] = ms[k];
+    a.v[k] = vs[k];
+    a.rows[k] = rows[k];
+  }
+  const double bc1 = 1.0 - std::pow((double)hp->beta1, (double)hp->step);
+  const double bc2 = 1.0 - std::pow((double)hp->beta2, (double)hp->step);
+  for (int k = 0; k < 6; k++) a.step_size[k] = (float)((double)hp->lr[k] / bc1);
+  a.bc2_sqrt = (float)std::sqrt(bc2);
+  a.beta1 = hp->beta1;
+  a.beta2 = hp->beta2;
+  a.eps = hp->eps;
+  a.n = plan->prob.n;
+  a.visible = visible_bits;
+  HIPCHK(launch_adam(a, 11 + 3 * K, stream), "adam");
+  return GSR_OK;
+}
+
 gsr_status gsr_last_stage_times(gsr_plan *plan, gsr_stage_times *out) {
   if (!plan || !out) return GSR_ERR_INVALID_ARG;
   memset(out, 0, sizeof *out);

@@ -125,6 +125,22 @@ int launch_visibility(const KParams &p, const gsr_camera *cams, const KOpts &o, 
                       const float *aabb6, uint32_t *bits, uint8_t *keep_out, uint8_t *in_block,
                       void *stream);
 int launch_copy_pixels(const KWs &ws, float *T_out, uint32_t *last_out, void *stream);
+
+// Adam over the parameter planes (gsr_optim.hip).  Groups: means (3 rows),
+// log_scales (3), quats (4), opacity_logits (1), sh (3K); step_size per
+// learning-rate slot = lr / (1 - beta1^t), bc2_sqrt = sqrt(1 - beta2^t).
+struct KAdam {
+  float *p[5];
+  const float *g[5];
+  float *m[5];
+  float *v[5];
+  int rows[5];
+  float step_size[6];
+  float bc2_sqrt, beta1, beta2, eps;
+  int64_t n;
+  const uint32_t *visible;
+};
+int launch_adam(const KAdam &a, int planes, void *stream);
 int launch_count_visible(const KWs &ws, int64_t n, int n_views, void *stream);
 int launch_tile_order(const KWs &ws, void *stream);
 

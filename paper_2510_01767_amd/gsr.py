@@ -91,8 +91,12 @@ class gsr_stage_times(ctypes.Structure):
         return {self.name[k].value.decode(): (float(self.ms[k]), int(self.launches[k])) for k in range(self.count)}
 
 
+class gsr_adam(ctypes.Structure):
+    _fields_ = [("lr", _f32 * 6), ("beta1", _f32), ("beta2", _f32), ("eps", _f32), ("step", _i32)]
+
+
 EXPORTS = (
-    "gsr_last_stage_times",
+    "gsr_last_stage_times", "gsr_adam_step",
     "gsr_default_options", "gsr_plan_create", "gsr_plan_destroy", "gsr_workspace_size",
     "gsr_workspace_layout", "gsr_image_offset", "gsr_forward", "gsr_backward",
     "gsr_forward_backward_l1", "gsr_visibility_mask", "gsr_graph_capture", "gsr_graph_launch",
@@ -134,6 +138,8 @@ def load(build_if_missing: bool = True):
     L.gsr_autotune.argtypes = [_vp, P(gsr_gaussians), _vp, _vp, _vp, _vp, P(gsr_grads), _vp, _sz, _i32,
                                P(gsr_options), P(_f32), _vp]
     L.gsr_last_stage_times.argtypes = [_vp, P(gsr_stage_times)]
+    L.gsr_adam_step.argtypes = [_vp, P(gsr_adam), P(gsr_grads), P(gsr_grads), P(gsr_grads), P(gsr_grads), _vp,
+                                _vp]
     L.gsr_plan_options.argtypes = [_vp, P(gsr_options)]
     L.gsr_plan_set_tuning.argtypes = [_vp, P(gsr_options)]
     L.gsr_status_string.argtypes = [_i32]
@@ -216,6 +222,11 @@ def gsr_visibility_mask(plan, g, cams, aabb, view_bits, keep_out, in_block, ws, 
     box = (_f32 * 6)(*aabb) if aabb is not None else None
     _check(load().gsr_visibility_mask(plan, ctypes.byref(g), cams, box, view_bits, keep_out, in_block, ws,
                                       ws_bytes, stream), plan)
+
+
+def gsr_adam_step(plan, hp, params, grads, m, v, visible_bits, stream):
+    _check(load().gsr_adam_step(plan, ctypes.byref(hp), ctypes.byref(params), ctypes.byref(grads),
+                                ctypes.byref(m), ctypes.byref(v), visible_bits, stream), plan)
 
 
 def gsr_graph_capture(plan, g, cams, targets, images, loss, grads, stats, ws, ws_bytes, stream):

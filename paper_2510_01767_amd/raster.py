@@ -183,6 +183,16 @@ class Rasterizer:
             o.grid_per_cu = grid_per_cu
         C.gsr_plan_set_tuning(self.plan, o)
 
+    def adam_step(self, params, grads, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, visible_only=False,
+                  stream=None):
+        """gsr_adam_step on parameter / gradient / moment dicts (PARAM_NAMES keys).  lr: six learning
+        rates (means, log_scales, quats, opacity_logits, SH band 0, SH bands >= 1).  visible_only:
+        update only the Gaussians visible in this plan's last step (its workspace view masks)."""
+        hp = C.gsr_adam((ctypes.c_float * 6)(*lr), beta1, beta2, eps, int(step))
+        bits = self.ws.data_ptr() + self.layout.view_bits if visible_only else None
+        C.gsr_adam_step(self.plan, hp, self.grads_struct(params), self.grads_struct(grads), self.grads_struct(m),
+                        self.grads_struct(v), bits, self.stream_handle(stream))
+
     # ------------------------------------------------------------ workspace views
     def ws_tensor(self, field, dtype, count):
         off = getattr(self.layout, field)

@@ -164,3 +164,21 @@ def test_status_strings():
     for s in range(7):
         assert C.gsr_status_string(s)
     assert C.gsr_status_string(3) == "intersection capacity exceeded"
+
+
+def test_adam_step_rejects_bad_arguments_before_touching_the_device():
+    s, plan = create(problem(), C.gsr_default_options())
+    assert s == C.GSR_OK
+    L = C.load()
+    g = C.gsr_grads(1, 1, 1, 1, 1)
+    hp = C.gsr_adam((ctypes.c_float * 6)(*([1e-3] * 6)), 0.9, 0.999, 1e-15, 0)
+    assert L.gsr_adam_step(plan, ctypes.byref(hp), ctypes.byref(g), ctypes.byref(g), ctypes.byref(g),
+                           ctypes.byref(g), None, None) == C.GSR_ERR_INVALID_ARG  # step 0
+    hp.step, hp.beta1 = 1, 1.0
+    assert L.gsr_adam_step(plan, ctypes.byref(hp), ctypes.byref(g), ctypes.byref(g), ctypes.byref(g),
+                           ctypes.byref(g), None, None) == C.GSR_ERR_INVALID_ARG  # beta1 = 1
+    hp.beta1 = 0.9
+    null = C.gsr_grads(None, 1, 1, 1, 1)
+    assert L.gsr_adam_step(plan, ctypes.byref(hp), ctypes.byref(null), ctypes.byref(g), ctypes.byref(g),
+                           ctypes.byref(g), None, None) == C.GSR_ERR_INVALID_ARG
+    C.gsr_plan_destroy(plan)
