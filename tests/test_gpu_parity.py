@@ -128,25 +128,28 @@ def test_records_and_binning_bit_exact(scene_name, c0, ragged):
             hit = al >= amin * (1 - 1e-5)
             if hit.any():
                 assert np.sqrt(dx[hit] ** 2 + dy[hit] ** 2).max() <= reach[k], (v, i)
-    # binning and order: feed the GPU's own rectangles and depth keys to the
-    # oracle's integer binning; the result must be identical
-    r3 = rec[:, 12:16].view(np.uint32)
-    rect = np.stack([r3[:, 0] & 0xffff, r3[:, 0] >> 16, r3[:, 1] & 0xffff, r3[:, 1] >> 16]).astype(np.int32)
-    visible = np.concatenate([((bits >> v) & 1) for v in range(V)]).astype(np.int32)
-    depth_bits = np.ascontiguousarray(rec[:, 14]).view(np.uint32)
-    tiebreak = np.tile(np.arange(n, dtype=np.int64), V)
-    tile_base = np.repeat(ora["tile_base"], n)
-    tiles_x = np.repeat(np.array([g[0] for g in ora["grids"]], np.int32), n)
-    b = oracle.bin_records(rect, visible, depth_bits, tiebreak, tile_base, tiles_x, L.tiles_total)
+    # binning and order against the oracle's own binning of its own records:
+    # bit-identical bucket sizes, starts, record order and depth keys in every
+    # tile that lists no Gaussian with an ambiguous decision
+    ob = ora["bins"]
     starts = parity.ws_np(r, "tile_start", torch.int32, L.tiles_total + 1).view(np.uint32).astype(np.int64)
-    keys = parity.ws_np(r, "keys", torch.int64, b["count"]).view(np.uint64)
-    assert starts[-1] == b["count"]
-    counts = np.diff(starts)
-    assert np.array_equal(counts, b["ranges"][:, 1] - b["ranges"][:, 0])
-    nonempty = counts > 0
-    assert np.array_equal(starts[:-1][nonempty], b["ranges"][nonempty, 0])
-    assert np.array_equal((keys & 0xffffffff).astype(np.int64), b["values"])
-    assert np.array_equal((keys >> 32).astype(np.uint32), b["depth"])
+    keys = parity.ws_np(r, "keys", torch.int64, int(starts[-1])).view(np.uint64)
+    amb_rec = np.concatenate([ora["records"][v]["margin"] < parity.DELTA for v in range(V)])
+    clean = 0
+    for t in range(L.tiles_total):
+        a0, a1 = ob["ranges"][t]
+        vals = ob["values"][a0:a1]
+        if amb_rec[vals].any():
+            continue
+        g = keys[starts[t]:starts[t + 1]]
+        assert np.array_equal((g & 0xffffffff).astype(np.int64), vals), t
+        assert np.array_equal((g >> 32).astype(np.uint32), ob["depth"][a0:a1]), t
+        clean += 1
+    assert clean == L.tiles_total  # these scenes have no ambiguous Gaussian
+    assert starts[-1] == ob["count"]
+    assert np.array_equal(np.diff(starts), ob["ranges"][:, 1] - ob["ranges"][:, 0])
+    nonempty = np.diff(starts) > 0
+    assert np.array_equal(starts[:-1][nonempty], ob["ranges"][nonempty, 0])
 
 
 @pytest.mark.parametrize("red", [0, 1, 2, 3])
