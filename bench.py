@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-adam", action="store_true")
+    ap.add_argument("--no-fcs", action="store_true")
     ap.add_argument("--tile", default=None, help="fixed tile shape WxH (with --no-autotune)")
     ap.add_argument("--lds-batch", type=int, default=256, help="with --no-autotune")
     ap.add_argument("--grid-per-cu", type=int, default=8, help="with --no-autotune")
@@ -158,6 +159,12 @@ def main():
     log(f"batched graph step {ms_batched:.3f} ms (wall {1000 * wall / args.steps:.3f} ms)")
     counts = rb.counts()
     images_gpu = rb.images.cpu().numpy()
+    # the smallest view's 2D gradients of the timed step, for the parity check (later
+    # stages reuse the workspace)
+    v_small = int(np.argmin([w * h for w, h in sizes]))
+    S_ = C.GSR_SLOT_FLOATS
+    g2d_small = rb.ws_tensor("grad2d", torch.float32, S_ * rb.layout.vn).view(-1, S_)[
+        v_small * scene.n:(v_small + 1) * scene.n, :9].cpu().numpy().astype(np.float64)
     loss_gpu = float(rb.loss.item())
     last = rb.ws_tensor("pix_last", torch.int32, rb.pixels).cpu().numpy().astype(np.int64)
     pairs = int(last.sum())
@@ -242,6 +249,34 @@ def main():
         log(f"adam: {adam}")
         del pa, ma, va
 
+    # ---- fast camera selection: one depth-compositing pass over the views, then the
+    # back-projected pixels counted into a 4 x 4 grid of blocks over the scene
+    fcs = None
+    if not args.no_fcs:
+        m = scene.means.astype(np.float64)
+        lo, hi = m.min(axis=1) - 1.0, m.max(axis=1) + 1.0
+        xs, ys = np.linspace(lo[0], hi[0], 5), np.linspace(lo[1], hi[1], 5)
+        blocks = torch.tensor([(xs[i], ys[j], lo[2], xs[i + 1], ys[j + 1], hi[2]) for i in range(4) for j in range(4)],
+                              dtype=torch.float32, device="cuda")
+        depth_img = torch.empty(3 * rb.pixels, dtype=torch.float32, device="cuda")
+        _, depth = rb.render_depth(params, cams, images=depth_img, stream=stream)
+        rb.camera_coverage(cams, depth, blocks, stream=stream)
+        f0, f1, f2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        f0.record(stream)
+        for _ in range(args.steps):
+            _, depth = rb.render_depth(params, cams, images=depth_img, stream=stream)
+        f1.record(stream)
+        for _ in range(args.steps):
+            counts_fcs, ratio, sel = rb.camera_coverage(cams, depth, blocks, stream=stream)
+        f2.record(stream)
+        torch.cuda.synchronize()
+        ms_depth, ms_cov = f0.elapsed_time(f1) / args.steps, f1.elapsed_time(f2) / args.steps
+        fcs = {"depth_render_ms": round(ms_depth, 4), "coverage_ms": round(ms_cov, 4), "blocks": 16,
+               "views_selected": int(sel.sum().item()),
+               "depth_mpixels_per_s": round(scene.pixels / (ms_depth * 1e-3) / 1e6, 1)}
+        log(f"fcs: {fcs}")
+        del depth_img
+
     # ---- algorithmic work of the dominant kernel
     n, V = scene.n, scene.n_views
     P = scene.pixels
@@ -298,9 +333,8 @@ def main():
                 amb = fo["ambiguous"][0].astype(bool)
                 err = np.abs(img_g - img_o) / np.maximum(1.0, np.abs(img_o))
                 rel_l2 = float(np.linalg.norm(img_g - img_o) / np.linalg.norm(img_o))
-                S = C.GSR_SLOT_FLOATS
-                g2d = rb.ws_tensor("grad2d", torch.float32, S * rb.layout.vn).view(-1, S)[v * n:(v + 1) * n, :9]
-                g2d = g2d.cpu().numpy().astype(np.float64)
+                assert v == v_small
+                g2d = g2d_small
                 go = bo["g2d"].T
                 visv = fo["records"][0]["visible"].astype(bool)
                 g_rel = float(np.linalg.norm(g2d[visv] - go[visv]) / np.linalg.norm(go[visv]))
@@ -348,6 +382,7 @@ def main():
         "counts": {"visible": vis, "union": counts.visible_union, "intersections": I, "pairs": pairs},
         "roofline": roof,
         "adam": adam,
+        "fcs": fcs,
         "parity": parity,
         "cpu_baseline": cpu,
     }

@@ -268,6 +268,33 @@ gsr_status gsr_plan_options(const gsr_plan *plan, gsr_options *opt);
  * grid_per_cu) of a plan; drops a captured graph. */
 gsr_status gsr_plan_set_tuning(gsr_plan *plan, const gsr_options *opt);
 
+/* ---- Fast camera selection (Sec. 3.2) -----------------------------------
+ * gsr_render_depth: gsr_forward (same images) plus the per-pixel depth of
+ * the blending sum, D = sum_i d_i alpha_i T_i with d_i the camera-space depth
+ * of Gaussian i's mean, under the same skip and stop rules as the colour
+ * (the depth form of the blending equation, Sec. 3.2; not normalised by the
+ * accumulated opacity).  depth: device [sum_v H_v W_v] floats, packed by view
+ * in input order, row-major.
+ *
+ * gsr_camera_coverage: the visibility ratio V_{c,b} of Sec. 3.2.  Each pixel
+ * (u, v) of each view is back-projected with its depth through its centre,
+ * p = R^T (D ((u + 1/2 - cx) / fx, (v + 1/2 - cy) / fy, 1) - t) (float64),
+ * and counted into every block that holds it; a block is the half-open box
+ * [min, max) of blocks[b] = (xmin, ymin, zmin, xmax, ymax, zmax) (device
+ * [n_blocks][6] floats, 1 <= n_blocks <= GSR_MAX_COVERAGE_BLOCKS).  Outputs
+ * (device, [n_views][n_blocks]): counts (cleared by the call), ratio =
+ * counts / (W H) (N_p = all pixels of the view) and selected = (ratio >= tau),
+ * the camera assignment C^(b) = {c | V_{c,b} >= tau}; ratio and selected may
+ * be NULL.  Uses no workspace; the plan gives the views' sizes. */
+#define GSR_MAX_COVERAGE_BLOCKS 1024
+
+gsr_status gsr_render_depth(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams, float *images,
+                            float *depth, void *ws, size_t ws_bytes, void *stream);
+
+gsr_status gsr_camera_coverage(gsr_plan *plan, const gsr_camera *cams, const float *depth, const float *blocks,
+                               int32_t n_blocks, float tau, uint32_t *counts, float *ratio, uint8_t *selected,
+                               void *stream);
+
 /* ---- Optimizer step (the NEXT stage after the reverse projection) ------
  * The paper locates the cost of Gaussians that no assigned camera sees in the
  * optimizer rather than in rendering (Sec. 3.3) and uses Sparse Adam in the

@@ -434,3 +434,52 @@ def adam_step(params: dict, grads: dict, m: dict, v: dict, lr, beta1: float, bet
         M[k] = np.where(upd, m_new, mk)
         V[k] = np.where(upd, v_new, vk)
     return P, M, V
+
+
+def back_project(depth: np.ndarray, cam: dict) -> np.ndarray:
+    """World points of a depth map (Sec. 3.2, fast camera selection): pixel
+    (u, v) with composited depth D lies on its centre's ray at camera depth D,
+    p = R^T (D ((u + 1/2 - cx)/fx, (v + 1/2 - cy)/fy, 1) - t).  [3][H][W]."""
+    H, W = depth.shape
+    R = np.asarray(cam["R"], np.float64).reshape(3, 3)
+    t = np.asarray(cam["t"], np.float64)
+    vs, us = np.mgrid[0:H, 0:W].astype(np.float64)
+    D = np.asarray(depth, np.float64)
+    xc = D * ((us + 0.5 - float(cam["cx"])) / float(cam["fx"]))
+    yc = D * ((vs + 0.5 - float(cam["cy"])) / float(cam["fy"]))
+    q = np.stack([xc - t[0], yc - t[1], D - t[2]])
+    return np.einsum("ab,bhw->ahw", R.T, q)
+
+
+def camera_coverage(depths: list, cams: list, blocks, tau: float = 0.1, margin_rel: float = 0.0,
+                    ambiguous: list | None = None):
+    """V_{c,b} = (1/N_p) sum_k 1[p_{c,k} in B_b] over the back-projected
+    pixels of each view (N_p = W H), blocks half-open boxes [min, max), and
+    the assignment C^(b) = {c | V_{c,b} >= tau} (Sec. 3.2).
+
+    With margin_rel > 0 it also counts, per (view, block), the points whose
+    membership could flip under a relative error margin_rel of their depth
+    (within margin_rel * D * |ray| of a face) or whose pixel is listed in
+    `ambiguous`; another correct depth map may count those either way."""
+    blocks = np.asarray(blocks, np.float64).reshape(-1, 6)
+    V, M = len(cams), blocks.shape[0]
+    counts = np.zeros((V, M), np.int64)
+    unsure = np.zeros((V, M), np.int64)
+    for v, (D, c) in enumerate(zip(depths, cams)):
+        p = back_project(D, c)
+        H, W = D.shape
+        fx, fy = float(c["fx"]), float(c["fy"])
+        vs, us = np.mgrid[0:H, 0:W].astype(np.float64)
+        ray = np.sqrt(((us + 0.5 - float(c["cx"])) / fx) ** 2 + ((vs + 0.5 - float(c["cy"])) / fy) ** 2 + 1.0)
+        slack = margin_rel * np.abs(np.asarray(D, np.float64)) * ray
+        amb = np.zeros((H, W), bool) if ambiguous is None else np.asarray(ambiguous[v], bool)
+        for b in range(M):
+            lo, hi = blocks[b, :3, None, None], blocks[b, 3:, None, None]
+            inside = np.all((p >= lo) & (p < hi), axis=0)
+            counts[v, b] = int(inside.sum())
+            if margin_rel > 0 or ambiguous is not None:
+                near = np.any((np.abs(p - lo) <= slack) | (np.abs(p - hi) <= slack), axis=0)
+                unsure[v, b] = int((near | amb).sum())
+    npix = np.array([c["W"] * c["H"] for c in cams], np.float64)[:, None]
+    ratio = counts / npix
+    return dict(counts=counts, ratio=ratio, selected=ratio >= tau, unsure=unsure)

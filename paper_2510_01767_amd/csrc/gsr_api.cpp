@@ -325,7 +325,7 @@ gsr_status zero_grads(gsr_plan *plan, const gsr_grads *g, void *stream) {
 // read-back of each view's intersection count (the plain form's only sync).
 // Batched: one chain for all views, no host synchronisation.
 gsr_status enqueue_front(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams, const KWs &ws,
-                         void *stream, bool plain_raster_fwd, float *images) {
+                         void *stream, bool plain_raster_fwd, float *images, float *depth = nullptr) {
   const ViewTable tbl = view_table(*plan);
   const KParams kp = kparams(*plan, g);
   const KOpts ko = kopts(*plan);
@@ -353,7 +353,8 @@ gsr_status enqueue_front(gsr_plan *plan, const gsr_gaussians *g, const gsr_camer
     STAGE(launch_emit(ws, plan->prob.n, V, v, stream), "emit");
     STAGE(launch_sort(ws, vi.tile_base, nt, stream), "sort");
     if (plain_raster_fwd)
-      STAGE(launch_raster_fwd(ws, ko, vi.tile_base, nt, images, V, use_history(*plan) ? 1 : 0, plan->opt.lds_batch, stream),
+      STAGE(launch_raster_fwd(ws, ko, vi.tile_base, nt, images, V, use_history(*plan) ? 1 : 0, plan->opt.lds_batch,
+                              depth, stream),
              "raster_fwd");
     base += iv;
   }
@@ -405,7 +406,8 @@ gsr_status enqueue_plain_l1(gsr_plan *plan, const gsr_gaussians *g, const gsr_ca
       return fail(plan, GSR_ERR_CAPACITY, "intersection capacity exceeded in view " + std::to_string(v));
     STAGE(launch_emit(ws, plan->prob.n, V, v, stream), "emit");
     STAGE(launch_sort(ws, vi.tile_base, nt, stream), "sort");
-    STAGE(launch_raster_fwd(ws, ko, vi.tile_base, nt, images, V, hist, plan->opt.lds_batch, stream), "raster_fwd");
+    STAGE(launch_raster_fwd(ws, ko, vi.tile_base, nt, images, V, hist, plan->opt.lds_batch, nullptr, stream),
+          "raster_fwd");
     STAGE(launch_l1(ws, ko, vi.tile_base, nt, images, targets, V, stream), "l1");
     STAGE(launch_raster_bwd(ws, ko, vi.tile_base, nt, ws.pix_dLdC, V, hist, plan->opt.lds_batch,
                             plan->opt.bwd_reduce, stream), "raster_bwd");
@@ -540,8 +542,9 @@ gsr_status gsr_plan_set_tuning(gsr_plan *plan, const gsr_options *t) {
   return GSR_OK;
 }
 
-gsr_status gsr_forward(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams, float *images,
-                       float *T_final, uint32_t *last, void *ws, size_t ws_bytes, void *stream) {
+static gsr_status forward_impl(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams, float *images,
+                               float *depth, float *T_final, uint32_t *last, void *ws, size_t ws_bytes,
+                               void *stream) {
   if (!plan) return GSR_ERR_INVALID_ARG;
   if (check_gaussians(g) != GSR_OK || !cams || !images) return fail(plan, GSR_ERR_INVALID_ARG, "null argument");
   gsr_status s = check_ws(plan, ws, ws_bytes);
@@ -550,17 +553,41 @@ gsr_status gsr_forward(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera 
   plan->forward_ready = false;
   stage_reset(plan);
   if (plan->opt.mode == GSR_MODE_PLAIN) {
-    s = enqueue_front(plan, g, cams, k, stream, true, images);
+    s = enqueue_front(plan, g, cams, k, stream, true, images, depth);
     if (s != GSR_OK) return s;
   } else {
     s = enqueue_front(plan, g, cams, k, stream, false, nullptr);
     if (s != GSR_OK) return s;
     STAGE(launch_raster_fwd(k, kopts(*plan), 0, k.tiles_total, images, plan->prob.n_views, use_history(*plan) ? 1 : 0,
-                             plan->opt.lds_batch, stream),
+                             plan->opt.lds_batch, depth, stream),
            "raster_fwd");
   }
   if (T_final || last) STAGE(launch_copy_pixels(k, T_final, last, stream), "copy");
   plan->forward_ready = true;
+  return GSR_OK;
+}
+
+gsr_status gsr_forward(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams, float *images,
+                       float *T_final, uint32_t *last, void *ws, size_t ws_bytes, void *stream) {
+  return forward_impl(plan, g, cams, images, nullptr, T_final, last, ws, ws_bytes, stream);
+}
+
+gsr_status gsr_render_depth(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams, float *images,
+                            float *depth, void *ws, size_t ws_bytes, void *stream) {
+  if (!depth) return plan ? fail(plan, GSR_ERR_INVALID_ARG, "null argument") : GSR_ERR_INVALID_ARG;
+  return forward_impl(plan, g, cams, images, depth, nullptr, nullptr, ws, ws_bytes, stream);
+}
+
+gsr_status gsr_camera_coverage(gsr_plan *plan, const gsr_camera *cams, const float *depth, const float *blocks,
+                               int32_t n_blocks, float tau, uint32_t *counts, float *ratio, uint8_t *selected,
+                               void *stream) {
+  if (!plan) return GSR_ERR_INVALID_ARG;
+  if (!cams || !depth || !blocks || !counts) return fail(plan, GSR_ERR_INVALID_ARG, "null argument");
+  if (n_blocks < 1 || n_blocks > GSR_MAX_COVERAGE_BLOCKS)
+    return fail(plan, GSR_ERR_INVALID_ARG, "n_blocks must be in [1, GSR_MAX_COVERAGE_BLOCKS]");
+  if (!std::isfinite(tau)) return fail(plan, GSR_ERR_INVALID_ARG, "tau must be finite");
+  HIPCHK(launch_coverage(view_table(*plan), cams, depth, blocks, n_blocks, tau, counts, ratio, selected, stream),
+         "coverage");
   return GSR_OK;
 }
 

@@ -1,0 +1,83 @@
+// Fast camera selection (Sec. 3.2) on gfx950: every pixel's composited
+// depth is back-projected through its pixel centre into world space and
+// counted into the block boxes that hold it; the ratio V_{c,b} = count / N_p
+// (N_p = the view's pixels) selects the cameras with V_{c,b} >= tau.
+//
+// Grid: x strides over a view's pixels, y is the view.  The boxes sit in
+// LDS, each workgroup counts in LDS and adds its counts to the global ones
+// with one atomic per (workgroup, block).  A second kernel turns counts into
+// ratios and the selection.
+#include <hip/hip_runtime.h>
+
+#include "gsr_device.h"
+
+namespace gsr {
+
+__global__ __launch_bounds__(kBlock) void k_coverage(ViewTable tbl, const gsr_camera *cams, const float *depth,
+                                                     const float *blocks, int n_blocks, uint32_t *counts) {
+  __shared__ float s_box[GSR_MAX_COVERAGE_BLOCKS * 6];
+  __shared__ uint32_t s_cnt[GSR_MAX_COVERAGE_BLOCKS];
+  for (int k = threadIdx.x; k < n_blocks * 6; k += blockDim.x) s_box[k] = blocks[k];
+  for (int k = threadIdx.x; k < n_blocks; k += blockDim.x) s_cnt[k] = 0u;
+  __syncthreads();
+  const int v = blockIdx.y;
+  const ViewInfo vi = tbl.v[v];
+  const gsr_camera c = cams[v];
+  const int64_t P = (int64_t)vi.W * vi.H;
+  for (int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pix < P; pix += (int64_t)gridDim.x * blockDim.x) {
+    const int px = (int)(pix % vi.W), py = (int)(pix / vi.W);
+    const double D = (double)depth[vi.pix_base + pix];
+    // camera frame point on the pixel's ray at depth D, minus t
+    const double q[3] = {D * (((double)px + 0.5 - (double)c.cx) / (double)c.fx) - (double)c.t[0],
+                         D * (((double)py + 0.5 - (double)c.cy) / (double)c.fy) - (double)c.t[1],
+                         D - (double)c.t[2]};
+    double w[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++)  // R^T q
+      w[a] = (double)c.R[a] * q[0] + (double)c.R[3 + a] * q[1] + (double)c.R[6 + a] * q[2];
+    for (int b = 0; b < n_blocks; b++) {
+      const float *bx = s_box + 6 * b;
+      const bool in = w[0] >= bx[0] && w[0] < bx[3] && w[1] >= bx[1] && w[1] < bx[4] && w[2] >= bx[2] && w[2] < bx[5];
+      // one LDS atomic per wavefront and block: the ballot's population
+      const uint64_t m = __ballot(in);
+      if (m && (uint64_t)(__ffsll((unsigned long long)__ballot(true)) - 1) == (uint64_t)lane_id())
+        atomicAdd(&s_cnt[b], (uint32_t)__popcll(m));
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < n_blocks; b += blockDim.x)
+    if (s_cnt[b]) atomicAdd(&counts[(int64_t)v * n_blocks + b], s_cnt[b]);
+}
+
+__global__ void k_coverage_ratio(ViewTable tbl, int n_blocks, float tau, const uint32_t *counts, float *ratio,
+                                 uint8_t *selected) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (int64_t)tbl.n_views * n_blocks) return;
+  const ViewInfo vi = tbl.v[k / n_blocks];
+  const float r = (float)((double)counts[k] / ((double)vi.W * (double)vi.H));
+  if (ratio) ratio[k] = r;
+  if (selected) selected[k] = r >= tau ? 1 : 0;
+}
+
+__global__ void k_zero_u32(uint32_t *p, int64_t count) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = 0u;
+}
+
+int launch_coverage(const ViewTable &views, const gsr_camera *cams, const float *depth, const float *blocks,
+                    int n_blocks, float tau, uint32_t *counts, float *ratio, uint8_t *selected, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nc = (int64_t)views.n_views * n_blocks;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((nc + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, counts, nc);
+  int64_t pmax = 1;
+  for (int v = 0; v < views.n_views; v++) pmax = std::max(pmax, (int64_t)views.v[v].W * views.v[v].H);
+  const unsigned gx = (unsigned)std::min((pmax + kBlock - 1) / kBlock, (int64_t)1024);
+  hipLaunchKernelGGL(k_coverage, dim3(gx, (unsigned)views.n_views), dim3(kBlock), 0, s, views, cams, depth, blocks,
+                     n_blocks, counts);
+  if (ratio || selected)
+    hipLaunchKernelGGL(k_coverage_ratio, dim3((unsigned)((nc + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, views,
+                       n_blocks, tau, counts, ratio, selected);
+  return last_err();
+}
+
+}  // namespace gsr

@@ -111,7 +111,7 @@ int launch_scan(const KWs &ws, int64_t tile_lo, int64_t tile_hi, int64_t base, i
 int launch_emit(const KWs &ws, int64_t n, int n_views, int view_only, void *stream);
 int launch_sort(const KWs &ws, int64_t tile_lo, int64_t tile_count, void *stream);
 int launch_raster_fwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, float *images,
-                      int n_views, int store_history, int lds_batch, void *stream);
+                      int n_views, int store_history, int lds_batch, float *depth, void *stream);
 int launch_l1(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *images,
               const float *targets, int n_views, void *stream);
 int launch_raster_bwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *dLdC,
@@ -141,6 +141,11 @@ struct KAdam {
   const uint32_t *visible;
 };
 int launch_adam(const KAdam &a, int planes, void *stream);
+
+// Fast camera selection (gsr_fcs.hip): back-projected depth pixels counted
+// per (view, block) box, the ratio to the view's pixel count and tau.
+int launch_coverage(const ViewTable &views, const gsr_camera *cams, const float *depth, const float *blocks,
+                    int n_blocks, float tau, uint32_t *counts, float *ratio, uint8_t *selected, void *stream);
 int launch_count_visible(const KWs &ws, int64_t n, int n_views, void *stream);
 int launch_tile_order(const KWs &ws, void *stream);
 

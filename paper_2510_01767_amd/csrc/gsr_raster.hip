@@ -101,15 +101,18 @@ __device__ __forceinline__ bool reaches_strip(const LdsRec &R, const TileCtx &c)
   return qmin <= -2.0f * R.r2.w * 1.0001f + 1e-4f;
 }
 
-__device__ __forceinline__ void load_batch(const KWs &ws, int64_t lo, int nb, LdsRec *s_rec, uint32_t *s_idx) {
+__device__ __forceinline__ void load_batch(const KWs &ws, int64_t lo, int nb, LdsRec *s_rec, uint32_t *s_idx,
+                                           float *s_depth = nullptr) {
   if ((int)threadIdx.x < nb) {
     const uint32_t r = (uint32_t)ws.keys[lo + threadIdx.x];
     const float4 *rec = rec_ptr(ws, r);
     s_rec[threadIdx.x].r0 = rec[0];
     s_rec[threadIdx.x].r1 = rec[1];
     s_rec[threadIdx.x].r2 = rec[2];
-    s_rec[threadIdx.x].reach = __uint_as_float(reinterpret_cast<const uint4 *>(rec)[3].w);
+    const uint4 r3 = reinterpret_cast<const uint4 *>(rec)[3];
+    s_rec[threadIdx.x].reach = __uint_as_float(r3.w);
     if (s_idx) s_idx[threadIdx.x] = r;
+    if (s_depth) s_depth[threadIdx.x] = __uint_as_float(r3.z);
   }
 }
 
@@ -142,10 +145,13 @@ struct Resident {
 // transmittance in front of it (0 when the entry was skipped).  Batches
 // start at c.start + k B; the last one loaded stays resident (`res`).  The
 // pair update is branch-free: a skipped pair adds 0 * colour and keeps T.
-template <int B, bool HIST>
+// With DEPTH it also composites the records' depths, D = sum d alpha T
+// (the depth form of the blending sum, Sec. 3.2), from s_depth.
+template <int B, bool HIST, bool DEPTH = false>
 __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsRec *s_rec,
                                              uint32_t *s_idx, uint16_t (*s_list)[B], float C[3], float &T,
-                                             int &last, float *hist, Resident &res) {
+                                             int &last, float *hist, Resident &res, float *s_depth = nullptr,
+                                             float *D = nullptr) {
   const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
   const int wave = threadIdx.x >> 6;
   T = 1.0f;
@@ -157,7 +163,7 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
   for (int64_t b = c.start; b < c.end; b += B) {
     if (__syncthreads_and(done)) break;
     const int nb = (int)min((int64_t)B, c.end - b);
-    load_batch(ws, b, nb, s_rec, s_idx);
+    load_batch(ws, b, nb, s_rec, s_idx, DEPTH ? s_depth : nullptr);
     __syncthreads();
     const int cnt = strip_list<B>(s_rec, nb, c, s_list[wave]);
     __syncthreads();
@@ -176,6 +182,7 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
       C[0] = __fmaf_rn(w, R.r2.x, C[0]);
       C[1] = __fmaf_rn(w, R.r2.y, C[1]);
       C[2] = __fmaf_rn(w, R.r2.z, C[2]);
+      if (DEPTH) *D = __fmaf_rn(w, s_depth[j], *D);
       if (HIST && !stop) hist[(b + j) * 256 + threadIdx.x] = take ? T : 0.0f;
       T = take ? Tn : T;
       last = stop ? (int)(b + j - c.start) : last;
@@ -334,10 +341,11 @@ __device__ __forceinline__ float block_sum_fixed(float x, float *s_w) {
   return r;
 }
 
-template <int TW, int TH, int B, bool HIST>
+template <int TW, int TH, int B, bool HIST, bool DEPTH>
 __global__ __launch_bounds__(kBlock) void k_raster_fwd(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
-                                                       float *images, int n_views) {
+                                                       float *images, int n_views, float *depth) {
   __shared__ LdsRec s_rec[B];
+  __shared__ float s_depth[DEPTH ? B : 1];
   __shared__ uint16_t s_list[4][B];
   __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
   for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
@@ -349,7 +357,8 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(KWs ws, KOpts o, int64_t 
   float C[3], T;
   int last;
   Resident res;
-  tile_forward<B, HIST>(ws, o, c, s_rec, nullptr, s_list, C, T, last, ws.history, res);
+  float D = 0.0f;
+  tile_forward<B, HIST, DEPTH>(ws, o, c, s_rec, nullptr, s_list, C, T, last, ws.history, res, s_depth, &D);
   if (c.inside) {
     const int64_t P = (int64_t)c.vi.W * c.vi.H;
     float *img = images + c.vi.pix_base * 3;
@@ -357,6 +366,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(KWs ws, KOpts o, int64_t 
     for (int ch = 0; ch < 3; ch++) img[ch * P + c.pix] = __fmaf_rn(T, o.bg[ch], C[ch]);
     ws.pix_T[c.vi.pix_base + c.pix] = T;
     ws.pix_last[c.vi.pix_base + c.pix] = (uint32_t)last;
+    if (DEPTH) depth[c.vi.pix_base + c.pix] = D;
   }
 }
 
@@ -554,18 +564,21 @@ int launch_tile_order(const KWs &ws, void *stream) {
   } while (0)
 
 int launch_raster_fwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, float *images,
-                      int n_views, int store_history, int lds_batch, void *stream) {
+                      int n_views, int store_history, int lds_batch, float *depth, void *stream) {
   if (tile_count <= 0) return 0;
   const dim3 grid((unsigned)xcd_grid(tile_count)), block(kBlock);
   hipStream_t s = (hipStream_t)stream;
 #define CALL_FWD(a, b_, B)                                                                                       \
   do {                                                                                                             \
-    if (store_history)                                                                                             \
-      hipLaunchKernelGGL((k_raster_fwd<a, b_, B, true>), grid, block, 0, s, ws, o, tile_lo, tile_count, images,    \
-                         n_views);                                                                                 \
+    if (depth)                                                                                                     \
+      hipLaunchKernelGGL((k_raster_fwd<a, b_, B, false, true>), grid, block, 0, s, ws, o, tile_lo, tile_count,     \
+                         images, n_views, depth);                                                                  \
+    else if (store_history)                                                                                        \
+      hipLaunchKernelGGL((k_raster_fwd<a, b_, B, true, false>), grid, block, 0, s, ws, o, tile_lo, tile_count,     \
+                         images, n_views, depth);                                                                  \
     else                                                                                                           \
-      hipLaunchKernelGGL((k_raster_fwd<a, b_, B, false>), grid, block, 0, s, ws, o, tile_lo, tile_count, images,   \
-                         n_views);                                                                                 \
+      hipLaunchKernelGGL((k_raster_fwd<a, b_, B, false, false>), grid, block, 0, s, ws, o, tile_lo, tile_count,    \
+                         images, n_views, depth);                                                                  \
   } while (0)
   GSR_TILE_DISPATCH(16, 16, CALL_FWD)
   GSR_TILE_DISPATCH(32, 8, CALL_FWD)

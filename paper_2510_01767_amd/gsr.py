@@ -24,6 +24,7 @@ GSR_ERR_HIP = 5
 GSR_ERR_STATE = 6
 GSR_MAX_VIEWS = 32
 GSR_SLOT_FLOATS = 16
+GSR_MAX_COVERAGE_BLOCKS = 1024
 GSR_MODE_PLAIN = 0
 GSR_MODE_BATCHED = 1
 GSR_BWD_AUTO = 0
@@ -96,7 +97,7 @@ class gsr_adam(ctypes.Structure):
 
 
 EXPORTS = (
-    "gsr_last_stage_times", "gsr_adam_step",
+    "gsr_last_stage_times", "gsr_adam_step", "gsr_render_depth", "gsr_camera_coverage",
     "gsr_default_options", "gsr_plan_create", "gsr_plan_destroy", "gsr_workspace_size",
     "gsr_workspace_layout", "gsr_image_offset", "gsr_forward", "gsr_backward",
     "gsr_forward_backward_l1", "gsr_visibility_mask", "gsr_graph_capture", "gsr_graph_launch",
@@ -138,6 +139,8 @@ def load(build_if_missing: bool = True):
     L.gsr_autotune.argtypes = [_vp, P(gsr_gaussians), _vp, _vp, _vp, _vp, P(gsr_grads), _vp, _sz, _i32,
                                P(gsr_options), P(_f32), _vp]
     L.gsr_last_stage_times.argtypes = [_vp, P(gsr_stage_times)]
+    L.gsr_render_depth.argtypes = [_vp, P(gsr_gaussians), _vp, _vp, _vp, _vp, _sz, _vp]
+    L.gsr_camera_coverage.argtypes = [_vp, _vp, _vp, _vp, _i32, _f32, _vp, _vp, _vp, _vp]
     L.gsr_adam_step.argtypes = [_vp, P(gsr_adam), P(gsr_grads), P(gsr_grads), P(gsr_grads), P(gsr_grads), _vp,
                                 _vp]
     L.gsr_plan_options.argtypes = [_vp, P(gsr_options)]
@@ -222,6 +225,15 @@ def gsr_visibility_mask(plan, g, cams, aabb, view_bits, keep_out, in_block, ws, 
     box = (_f32 * 6)(*aabb) if aabb is not None else None
     _check(load().gsr_visibility_mask(plan, ctypes.byref(g), cams, box, view_bits, keep_out, in_block, ws,
                                       ws_bytes, stream), plan)
+
+
+def gsr_render_depth(plan, g, cams, images, depth, ws, ws_bytes, stream):
+    _check(load().gsr_render_depth(plan, ctypes.byref(g), cams, images, depth, ws, ws_bytes, stream), plan)
+
+
+def gsr_camera_coverage(plan, cams, depth, blocks, n_blocks, tau, counts, ratio, selected, stream):
+    _check(load().gsr_camera_coverage(plan, cams, depth, blocks, n_blocks, tau, counts, ratio, selected, stream),
+           plan)
 
 
 def gsr_adam_step(plan, hp, params, grads, m, v, visible_bits, stream):

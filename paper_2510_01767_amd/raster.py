@@ -183,6 +183,25 @@ class Rasterizer:
             o.grid_per_cu = grid_per_cu
         C.gsr_plan_set_tuning(self.plan, o)
 
+    def render_depth(self, params, cams, keep=None, images=None, stream=None):
+        """gsr_render_depth: (images [3P], depth [P]) with D = sum_i d_i alpha_i T_i per pixel."""
+        img = self.images if images is None else images
+        depth = torch.empty(self.pixels, dtype=torch.float32, device=self.device)
+        C.gsr_render_depth(self.plan, self.gaussians(params, keep), cams.data_ptr(), img.data_ptr(),
+                           depth.data_ptr(), self.ws.data_ptr(), self.ws_bytes, self.stream_handle(stream))
+        return img, depth
+
+    def camera_coverage(self, cams, depth, blocks, tau=0.1, stream=None):
+        """gsr_camera_coverage: counts [V][M] (int32 view of u32), ratio V_{c,b} [V][M], selected [V][M]."""
+        assert blocks.dtype == torch.float32 and blocks.is_contiguous() and blocks.shape[-1] == 6
+        M = blocks.shape[0]
+        counts = torch.empty((self.V, M), dtype=torch.int32, device=self.device)
+        ratio = torch.empty((self.V, M), dtype=torch.float32, device=self.device)
+        selected = torch.empty((self.V, M), dtype=torch.uint8, device=self.device)
+        C.gsr_camera_coverage(self.plan, cams.data_ptr(), depth.data_ptr(), blocks.data_ptr(), M, float(tau),
+                              counts.data_ptr(), ratio.data_ptr(), selected.data_ptr(), self.stream_handle(stream))
+        return counts, ratio, selected
+
     def adam_step(self, params, grads, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, visible_only=False,
                   stream=None):
         """gsr_adam_step on parameter / gradient / moment dicts (PARAM_NAMES keys).  lr: six learning
