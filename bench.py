@@ -80,6 +80,7 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-adam", action="store_true")
     ap.add_argument("--no-fcs", action="store_true")
+    ap.add_argument("--no-partition", action="store_true")
     ap.add_argument("--tile", default=None, help="fixed tile shape WxH (with --no-autotune)")
     ap.add_argument("--lds-batch", type=int, default=256, help="with --no-autotune")
     ap.add_argument("--grid-per-cu", type=int, default=8, help="with --no-autotune")
@@ -101,7 +102,8 @@ def main():
 
     from paper_2510_01767_amd import gsr as C
     from paper_2510_01767_amd import scenes
-    from paper_2510_01767_amd.raster import Rasterizer, camera_tensor, pack_images, scene_tensors
+    from paper_2510_01767_amd.raster import (Rasterizer, camera_tensor, pack_images, partition_blocks_device,
+                                             scene_tensors)
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     C.load(build_if_missing=False)
@@ -276,6 +278,32 @@ def main():
                "depth_mpixels_per_s": round(scene.pixels / (ms_depth * 1e-3) / 1e6, 1)}
         log(f"fcs: {fcs}")
         del depth_img
+
+        # ---- scene partition (Alg. 1) into 8 blocks: the back-projected pixels stay in HBM
+        # and every split counts them on the GPU; the host variant counts the same points
+        if not args.no_partition:
+            g0, g1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+            g0.record(stream)
+            pts = rb.back_project(cams, depth, stream=stream)
+            g1.record(stream)
+            torch.cuda.synchronize()
+            offsets = np.cumsum([0] + [c["W"] * c["H"] for c in scene.cameras]).astype(np.int64)
+            ms_dev = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                dev = partition_blocks_device(scene.block_aabb, scene.means, pts, offsets, 8, stream=stream)
+                ms_dev.append((time.perf_counter() - t0) * 1e3)
+            pts_host = pts.cpu().numpy()
+            t0 = time.perf_counter()
+            host = C.gsr_partition_blocks(scene.block_aabb, scene.means, pts_host, offsets, 8)
+            ms_host = (time.perf_counter() - t0) * 1e3
+            fcs["partition"] = {
+                "blocks": 8, "refine_steps": 3, "back_project_ms": round(g0.elapsed_time(g1), 4),
+                "device_ms": round(min(ms_dev), 3), "host_ms": round(ms_host, 1),
+                "device_matches_host": bool(np.array_equal(dev[0], host[0]) and np.array_equal(dev[1], host[1])),
+                "workloads": dev[2].tolist()}
+            log(f"partition: {fcs['partition']}")
+            del pts, pts_host
 
     # ---- algorithmic work of the dominant kernel
     n, V = scene.n, scene.n_views

@@ -295,6 +295,70 @@ gsr_status gsr_camera_coverage(gsr_plan *plan, const gsr_camera *cams, const flo
                                int32_t n_blocks, float tau, uint32_t *counts, float *ratio, uint8_t *selected,
                                void *stream);
 
+/* ---- Load-balanced KD-tree partition (Sec. 3.1, App. A.5) ---------------
+ * The tree is grown on the host; gsr_partition_blocks also counts the pixels
+ * on the host, gsr_partition_blocks_device counts them on the GPU.  Both give
+ * identical results for the same points. */
+#define GSR_MAX_REFINE_STEPS 16
+
+/*
+ * Splits the scene box (scene_aabb: xmin, ymin, zmin, xmax, ymax, zmax,
+ * half-open) into n_blocks leaves, best-first: while fewer than n_blocks
+ * leaves, the leaf with the most cameras (the earliest created among equals)
+ * is split orthogonally to the longer of its x / y extents (x on a tie).  The
+ * cut at percentile q is the order statistic of index floor(q (m - 1)) of the
+ * m Gaussian centres in the leaf along that axis (the extent's middle when
+ * m = 0); left child [min, cut), right [cut, max).  Each child receives the
+ * parent's cameras whose back-projected pixels fall into it with ratio >= tau
+ * (fast camera selection, Sec. 3.2).  Cutline refinement: q starts at 0.5
+ * (the median), q_low = q_min, q_high = q_max; for refine_steps evaluations
+ * (the paper uses 3, with q_min 0.1 and q_max 0.9): if the left child has more
+ * cameras, q_high = q and q = (q_low + q) / 2; if the right one has more,
+ * q_low = q and q = (q_high + q) / 2; on a tie stop.  The children of the last
+ * evaluated split are kept.  All on host memory, float comparisons:
+ * centers [3][n]; points [3][total] (x plane, y plane, z plane), the pixels of
+ * view v at [view_offsets[v], view_offsets[v + 1]) (view_offsets[0] = 0, all
+ * W H pixels of the view, e.g. from gsr_back_project); outputs blocks_out
+ * [n_blocks][6], assign_out [n_blocks][n_views] (1 = camera assigned; may be
+ * NULL), workload_out [n_blocks] (camera counts; may be NULL), leaves in
+ * creation order.  Needs no GPU and no plan; all buffers are the caller's.
+ * GSR_ERR_INVALID_ARG for a null required pointer, n < 0, n_views < 1,
+ * n_blocks < 1, refine_steps < 1, not 0 < q_min < q_max < 1, a non-finite
+ * tau, refine_steps > GSR_MAX_REFINE_STEPS, view_offsets[0] != 0 or
+ * decreasing offsets; outputs then untouched. */
+gsr_status gsr_partition_blocks(const float *scene_aabb, const float *centers, int64_t n, const float *points,
+                                const int64_t *view_offsets, int32_t n_views, int32_t n_blocks, float tau,
+                                int32_t refine_steps, float q_min, float q_max, float *blocks_out,
+                                uint8_t *assign_out, int32_t *workload_out);
+
+/* Bytes of device workspace gsr_partition_blocks_device needs for n_views
+ * cameras (about 4 KiB per camera).  GSR_ERR_INVALID_ARG for n_views < 1. */
+gsr_status gsr_partition_workspace_size(int32_t n_views, size_t *bytes);
+
+/* gsr_partition_blocks with the pixel counting on the GPU: `points` is
+ * DEVICE memory [3][total] (e.g. gsr_back_project's output, left resident);
+ * scene_aabb, centers, view_offsets and the three outputs are host memory.
+ * Per split, one kernel counts the parent's cameras' pixels into both
+ * children of every percentile the bisection can reach (when those
+ * 2 (2^refine_steps - 1) boxes fit in GSR_MAX_COVERAGE_BLOCKS, else of each
+ * evaluated split in turn), then the host walks the bisection.  Works on
+ * `stream` and synchronizes it once per split; ws is caller-owned device
+ * memory of gsr_partition_workspace_size bytes.  Errors as
+ * gsr_partition_blocks, plus GSR_ERR_WORKSPACE_TOO_SMALL and GSR_ERR_HIP. */
+gsr_status gsr_partition_blocks_device(const float *scene_aabb, const float *centers, int64_t n,
+                                       const float *points, const int64_t *view_offsets, int32_t n_views,
+                                       int32_t n_blocks, float tau, int32_t refine_steps, float q_min, float q_max,
+                                       void *ws, size_t ws_bytes, void *stream, float *blocks_out,
+                                       uint8_t *assign_out, int32_t *workload_out);
+
+/* The back-projected pixels of gsr_camera_coverage as points: points [3][P]
+ * (device, P = sum_v H_v W_v, view-major, row-major pixels; x plane, then y,
+ * then z), float64 arithmetic rounded to float32; depth is the [V][H][W]
+ * output of gsr_render_depth.  Enqueued on `stream`; GSR_ERR_INVALID_ARG for a
+ * null pointer, GSR_ERR_HIP if the launch fails. */
+gsr_status gsr_back_project(gsr_plan *plan, const gsr_camera *cams, const float *depth, float *points,
+                            void *stream);
+
 /* ---- Optimizer step (the NEXT stage after the reverse projection) ------
  * The paper locates the cost of Gaussians that no assigned camera sees in the
  * optimizer rather than in rendering (Sec. 3.3) and uses Sparse Adam in the

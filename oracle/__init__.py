@@ -482,4 +482,5 @@ def camera_coverage(depths: list, cams: list, blocks, tau: float = 0.1, margin_r
                 unsure[v, b] = int((near | amb).sum())
     npix = np.array([c["W"] * c["H"] for c in cams], np.float64)[:, None]
     ratio = counts / npix
-    return dict(counts=counts, ratio=ratio, selected=ratio >= tau, unsure=unsure)
+    # V >= tau with tau the float32 value: count >= tau N_p is exact in float64
+    return dict(counts=counts, ratio=ratio, selected=counts >= float(np.float32(tau)) * npix, unsure=unsure)

@@ -578,6 +578,14 @@ gsr_status gsr_render_depth(gsr_plan *plan, const gsr_gaussians *g, const gsr_ca
   return forward_impl(plan, g, cams, images, depth, nullptr, nullptr, ws, ws_bytes, stream);
 }
 
+gsr_status gsr_back_project(gsr_plan *plan, const gsr_camera *cams, const float *depth, float *points,
+                            void *stream) {
+  if (!plan) return GSR_ERR_INVALID_ARG;
+  if (!cams || !depth || !points) return fail(plan, GSR_ERR_INVALID_ARG, "null argument");
+  HIPCHK(launch_back_project(view_table(*plan), cams, depth, points, stream), "back-projection");
+  return GSR_OK;
+}
+
 gsr_status gsr_camera_coverage(gsr_plan *plan, const gsr_camera *cams, const float *depth, const float *blocks,
                                int32_t n_blocks, float tau, uint32_t *counts, float *ratio, uint8_t *selected,
                                void *stream) {

@@ -144,6 +144,34 @@ int launch_adam(const KAdam &a, int planes, void *stream);
 
 // Fast camera selection (gsr_fcs.hip): back-projected depth pixels counted
 // per (view, block) box, the ratio to the view's pixel count and tau.
+// Device workspace of the partition's pixel counting: the selected views'
+// pixel ranges, the candidate boxes and their counts.
+struct PartitionView {
+  int64_t first, count;
+};
+struct PartitionWs {
+  PartitionView *views;
+  float *boxes;
+  uint32_t *counts;
+};
+inline size_t partition_ws_bytes(int n_views) {
+  return 256 + (size_t)n_views * sizeof(PartitionView) + (size_t)GSR_MAX_COVERAGE_BLOCKS * 6 * sizeof(float) +
+         (size_t)n_views * GSR_MAX_COVERAGE_BLOCKS * sizeof(uint32_t);
+}
+inline PartitionWs partition_ws(char *ws, int n_views) {
+  char *p = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+  PartitionWs w;
+  w.views = (PartitionView *)p;
+  w.boxes = (float *)(p + (size_t)n_views * sizeof(PartitionView));
+  w.counts = (uint32_t *)((char *)w.boxes + (size_t)GSR_MAX_COVERAGE_BLOCKS * 6 * sizeof(float));
+  return w;
+}
+// counts[j][b] = number of points of view j (points [3][total], the view's
+// range in views[j]) inside box b, for j < n_sel and b < nb <= 1024
+int launch_count_points(const float *points, int64_t total, const PartitionView *views, int n_sel, int64_t pmax,
+                        const float *boxes, int nb, uint32_t *counts, void *stream);
+int launch_back_project(const ViewTable &views, const gsr_camera *cams, const float *depth, float *points,
+                        void *stream);
 int launch_coverage(const ViewTable &views, const gsr_camera *cams, const float *depth, const float *blocks,
                     int n_blocks, float tau, uint32_t *counts, float *ratio, uint8_t *selected, void *stream);
 int launch_count_visible(const KWs &ws, int64_t n, int n_views, void *stream);

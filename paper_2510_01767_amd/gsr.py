@@ -25,6 +25,7 @@ GSR_ERR_STATE = 6
 GSR_MAX_VIEWS = 32
 GSR_SLOT_FLOATS = 16
 GSR_MAX_COVERAGE_BLOCKS = 1024
+GSR_MAX_REFINE_STEPS = 16
 GSR_MODE_PLAIN = 0
 GSR_MODE_BATCHED = 1
 GSR_BWD_AUTO = 0
@@ -97,7 +98,8 @@ class gsr_adam(ctypes.Structure):
 
 
 EXPORTS = (
-    "gsr_last_stage_times", "gsr_adam_step", "gsr_render_depth", "gsr_camera_coverage",
+    "gsr_last_stage_times", "gsr_adam_step", "gsr_render_depth", "gsr_camera_coverage", "gsr_back_project",
+    "gsr_partition_blocks", "gsr_partition_workspace_size", "gsr_partition_blocks_device",
     "gsr_default_options", "gsr_plan_create", "gsr_plan_destroy", "gsr_workspace_size",
     "gsr_workspace_layout", "gsr_image_offset", "gsr_forward", "gsr_backward",
     "gsr_forward_backward_l1", "gsr_visibility_mask", "gsr_graph_capture", "gsr_graph_launch",
@@ -139,6 +141,12 @@ def load(build_if_missing: bool = True):
     L.gsr_autotune.argtypes = [_vp, P(gsr_gaussians), _vp, _vp, _vp, _vp, P(gsr_grads), _vp, _sz, _i32,
                                P(gsr_options), P(_f32), _vp]
     L.gsr_last_stage_times.argtypes = [_vp, P(gsr_stage_times)]
+    L.gsr_back_project.argtypes = [_vp, _vp, _vp, _vp, _vp]
+    L.gsr_partition_blocks.argtypes = [P(_f32), P(_f32), _i64, P(_f32), P(_i64), _i32, _i32, _f32, _i32, _f32,
+                                       _f32, P(_f32), P(ctypes.c_uint8), P(_i32)]
+    L.gsr_partition_workspace_size.argtypes = [_i32, P(_sz)]
+    L.gsr_partition_blocks_device.argtypes = [P(_f32), P(_f32), _i64, _vp, P(_i64), _i32, _i32, _f32, _i32, _f32,
+                                              _f32, _vp, _sz, _vp, P(_f32), P(ctypes.c_uint8), P(_i32)]
     L.gsr_render_depth.argtypes = [_vp, P(gsr_gaussians), _vp, _vp, _vp, _vp, _sz, _vp]
     L.gsr_camera_coverage.argtypes = [_vp, _vp, _vp, _vp, _i32, _f32, _vp, _vp, _vp, _vp]
     L.gsr_adam_step.argtypes = [_vp, P(gsr_adam), P(gsr_grads), P(gsr_grads), P(gsr_grads), P(gsr_grads), _vp,
@@ -234,6 +242,56 @@ def gsr_render_depth(plan, g, cams, images, depth, ws, ws_bytes, stream):
 def gsr_camera_coverage(plan, cams, depth, blocks, n_blocks, tau, counts, ratio, selected, stream):
     _check(load().gsr_camera_coverage(plan, cams, depth, blocks, n_blocks, tau, counts, ratio, selected, stream),
            plan)
+
+
+def gsr_back_project(plan, cams, depth, points, stream):
+    _check(load().gsr_back_project(plan, cams, depth, points, stream), plan)
+
+
+def _partition_host_args(scene_aabb, centers, view_offsets, n_blocks):
+    import numpy as np
+    aabb = np.ascontiguousarray(scene_aabb, np.float32)
+    c = np.ascontiguousarray(centers, np.float32)
+    off = np.ascontiguousarray(view_offsets, np.int64)
+    V = off.size - 1
+    out = (np.zeros((n_blocks, 6), np.float32), np.zeros((n_blocks, V), np.uint8), np.zeros(n_blocks, np.int32))
+    return aabb, c, off, V, out
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def gsr_partition_blocks(scene_aabb, centers, points, view_offsets, n_blocks, tau=0.1, refine_steps=3, q_min=0.1,
+                         q_max=0.9):
+    """Host KD-tree partition on NumPy arrays: centers [3][n], points [3][total] (float32),
+    view_offsets [V + 1] (int64).  Returns (blocks [M][6], assign [M][V] uint8, workload [M])."""
+    import numpy as np
+    aabb, c, off, V, (blocks, assign, work) = _partition_host_args(scene_aabb, centers, view_offsets, n_blocks)
+    pts = np.ascontiguousarray(points, np.float32)
+    P = ctypes.POINTER
+    _check(load().gsr_partition_blocks(_ptr(aabb, _f32), _ptr(c, _f32), c.shape[1], _ptr(pts, _f32), _ptr(off, _i64),
+                                       V, n_blocks, tau, refine_steps, q_min, q_max, _ptr(blocks, _f32),
+                                       _ptr(assign, ctypes.c_uint8), _ptr(work, _i32)), None)
+    return blocks, assign, work
+
+
+def gsr_partition_workspace_size(n_views):
+    out = _sz(0)
+    _check(load().gsr_partition_workspace_size(n_views, ctypes.byref(out)), None)
+    return out.value
+
+
+def gsr_partition_blocks_device(scene_aabb, centers, points_ptr, view_offsets, n_blocks, ws_ptr, ws_bytes, stream,
+                                tau=0.1, refine_steps=3, q_min=0.1, q_max=0.9):
+    """The same partition with the pixel counting on the GPU: points_ptr is the device address
+    of float32 [3][total] points; the rest are host NumPy arrays."""
+    aabb, c, off, V, (blocks, assign, work) = _partition_host_args(scene_aabb, centers, view_offsets, n_blocks)
+    _check(load().gsr_partition_blocks_device(_ptr(aabb, _f32), _ptr(c, _f32), c.shape[1], points_ptr,
+                                              _ptr(off, _i64), V, n_blocks, tau, refine_steps, q_min, q_max, ws_ptr,
+                                              ws_bytes, stream, _ptr(blocks, _f32), _ptr(assign, ctypes.c_uint8),
+                                              _ptr(work, _i32)), None)
+    return blocks, assign, work
 
 
 def gsr_adam_step(plan, hp, params, grads, m, v, visible_bits, stream):

@@ -43,6 +43,20 @@ def scene_tensors(scene, device="cuda") -> dict:
                 opacity_logits=t(scene.opacity_logits), sh=t(scene.sh))
 
 
+def partition_blocks_device(scene_aabb, centers, points, view_offsets, n_blocks, tau=0.1, refine_steps=3,
+                            q_min=0.1, q_max=0.9, stream=None):
+    """gsr_partition_blocks_device: the KD-tree partition with the pixel counting on the GPU.
+    points: float32 CUDA tensor [3][total]; the other inputs are host arrays.  Returns host
+    (blocks [M][6], assign [M][V] uint8, workload [M])."""
+    assert points.is_cuda and points.dtype == torch.float32 and points.is_contiguous() and points.shape[0] == 3
+    n_views = len(view_offsets) - 1
+    ws_bytes = C.gsr_partition_workspace_size(n_views)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=points.device)
+    s = torch.cuda.current_stream(points.device) if stream is None else stream
+    return C.gsr_partition_blocks_device(scene_aabb, centers, points.data_ptr(), view_offsets, n_blocks,
+                                         ws.data_ptr(), ws_bytes, s.cuda_stream, tau, refine_steps, q_min, q_max)
+
+
 class Rasterizer:
     """One plan + workspace for a fixed problem shape."""
 
@@ -201,6 +215,12 @@ class Rasterizer:
         C.gsr_camera_coverage(self.plan, cams.data_ptr(), depth.data_ptr(), blocks.data_ptr(), M, float(tau),
                               counts.data_ptr(), ratio.data_ptr(), selected.data_ptr(), self.stream_handle(stream))
         return counts, ratio, selected
+
+    def back_project(self, cams, depth, stream=None):
+        """gsr_back_project: the world points [3][P] of every pixel's composited depth."""
+        points = torch.empty((3, self.pixels), dtype=torch.float32, device=self.device)
+        C.gsr_back_project(self.plan, cams.data_ptr(), depth.data_ptr(), points.data_ptr(), self.stream_handle(stream))
+        return points
 
     def adam_step(self, params, grads, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, visible_only=False,
                   stream=None):

@@ -379,5 +379,48 @@ def small_ragged(seed=SEED_BASE + 100, n=3000, sh_degree=3, sizes=((150, 97), (6
 CONFIGS = {0: config0, 1: config1, 2: config2, 3: config3, 4: config4}
 
 
+@dataclasses.dataclass
+class PartitionInput:
+    """Inputs of the KD-tree partition: the scene box, coarse Gaussian
+    centres [3][n] and each camera's back-projected pixels as points
+    [3][total], camera v's at [offsets[v], offsets[v + 1])."""
+    aabb: np.ndarray     # (6,) float32
+    centers: np.ndarray  # [3][n] float32
+    points: np.ndarray   # [3][total] float32
+    offsets: np.ndarray  # [V + 1] int64
+
+
+def partition_input(seed=SEED_BASE + 200, n=20_000, n_views=24, pixels=(24 * 16, 48 * 32), half=100.0,
+                    hotspot=0.6):
+    """A city block with an uneven camera distribution: the centres are the
+    city points of the other workloads; each aerial camera sees a square
+    footprint (side 30-90 % of the block's half extent) and its pixels are
+    city points drawn from that footprint.  A fraction `hotspot` of the
+    cameras look near one corner, the rest anywhere, so that the per-block
+    camera counts are heterogeneous (the imbalance Sec. 3.1 addresses)."""
+    rng = np.random.default_rng(seed)
+    centres = _city_points(rng, n, half, max(4, n // 2000))
+    hot = rng.uniform(-0.8 * half, -0.3 * half, 2)
+    pts, offsets = [], [0]
+    for v in range(n_views):
+        c = hot + rng.normal(0.0, 0.15 * half, 2) if rng.uniform() < hotspot else rng.uniform(-0.8 * half, 0.8 * half, 2)
+        r = rng.uniform(0.15, 0.45) * half
+        inside = np.nonzero((np.abs(centres[0] - c[0]) < r) & (np.abs(centres[1] - c[1]) < r))[0]
+        k = int(rng.integers(pixels[0], pixels[1] + 1))
+        if inside.size == 0:
+            inside = np.arange(n)
+        pick = centres[:, rng.choice(inside, k)] + rng.normal(0.0, 0.2, (3, k))
+        pts.append(pick)
+        offsets.append(offsets[-1] + k)
+    c32 = _f32(centres)
+    c32[:2] = np.minimum(c32[:2], np.nextafter(np.float32(half), np.float32(-np.inf)))
+    # a half-open box that holds every float32 centre
+    aabb = np.array([-half, -half, c32[2].min(), half, half, np.nextafter(c32[2].max(), np.float32(np.inf))],
+                    np.float32)
+    assert np.all((c32 >= aabb[:3, None]) & (c32 < aabb[3:, None]))
+    return PartitionInput(aabb=aabb, centers=c32,
+                          points=_f32(np.concatenate(pts, axis=1)), offsets=np.asarray(offsets, np.int64))
+
+
 def make_config(k: int, **kw) -> Scene:
     return CONFIGS[k](**kw)

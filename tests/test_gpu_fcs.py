@@ -57,7 +57,8 @@ def check_coverage(r, cams, depth, blocks, fo, cameras):
     assert np.all(np.abs(c - ora["counts"]) <= ora["unsure"]), (c, ora["counts"], ora["unsure"])
     npix = np.array([cc["W"] * cc["H"] for cc in cameras], np.float64)[:, None]
     assert np.allclose(ratio.cpu().numpy(), c / npix, rtol=1e-6)
-    assert np.array_equal(sel.cpu().numpy().astype(bool), ratio.cpu().numpy() >= np.float32(0.1))
+    # V >= tau exactly: count >= tau N_p, tau the float32 value
+    assert np.array_equal(sel.cpu().numpy().astype(bool), c >= float(np.float32(0.1)) * npix)
     return c, ora
 
 
