@@ -359,6 +359,71 @@ gsr_status gsr_partition_blocks_device(const float *scene_aabb, const float *cen
 gsr_status gsr_back_project(gsr_plan *plan, const gsr_camera *cams, const float *depth, float *points,
                             void *stream);
 
+/* ---- Selective densification and pruning (Sec. 3.3) -------------------
+ * The fine stage densifies like vanilla 3DGS (App. A.1) except that only
+ * Gaussians inside the block may densify (selective densification).  Per
+ * Gaussian i, with S_i and n_i the statistics of gsr_stats:
+ *   - keep[i] = 0 (gsr_gaussians.keep, e.g. the in-block mask when the
+ *     blocks are merged, Fig. 1): no output;
+ *   - candidate when n_i > 0, S_i / n_i >= grad_threshold and, with
+ *     selective = 1, in_block[i] = 1;
+ *   - a candidate whose largest exp(log_scale) is <= clone_max_scale is
+ *     cloned: the original (keeping its optimizer moments) and a copy (zero
+ *     moments);
+ *   - any other candidate is split into two children that replace it:
+ *     child j's mean is mean + R(q/|q|) (exp(log_scale) * eps_j) with eps_j
+ *     = samples[j][0..2][i] (standard normal draws the caller makes), its
+ *     log scales are log_scale - ln(1.6) rounded to float (the scale divided
+ *     by 0.8 times two children), quaternion, opacity and SH copied, zero
+ *     moments;
+ *   - every output is pruned when sigmoid(opacity logit) < min_opacity
+ *     (min_opacity > 0) or its largest exp(log_scale) > max_world_scale
+ *     (max_world_scale > 0).
+ * The S_i / n_i, scale and opacity tests are made exactly on the float
+ * inputs (S_i >= threshold n_i in double; log scale and logit against the
+ * double logarithms of the thresholds).  Outputs of Gaussian i are written
+ * at the prefix sum of the output counts of Gaussians 0..i-1 (input order
+ * kept, a clone or the children next to their parent). */
+typedef struct gsr_densify_opts {
+  float grad_threshold;  /* densify when S / n >= this; +inf turns densification off */
+  float clone_max_scale; /* > 0: clone at or below this largest scale, split above */
+  float min_opacity;     /* in [0, 1); 0 turns the opacity pruning off */
+  float max_world_scale; /* <= 0 turns the size pruning off */
+  int32_t selective;     /* 1: only in_block Gaussians densify; 0: every Gaussian may */
+  int32_t reserved;      /* 0 */
+} gsr_densify_opts;
+
+/* Device workspace bytes of the densification of n Gaussians (8 bytes per
+ * 1024 Gaussians plus 16). */
+gsr_status gsr_densify_workspace_size(int64_t n, size_t *bytes);
+
+/* First half: decides every Gaussian and counts the outputs.  g (device
+ * planes of n Gaussians, keep optional), stats (both pointers required) and
+ * in_block (device [n] u8, required when selective = 1) are read on
+ * `stream`; the stream is synchronized and *n_out (host) receives the
+ * output count.  The workspace keeps the per-block offsets for
+ * gsr_densify_apply.  GSR_ERR_INVALID_ARG for n < 0, sh_degree outside
+ * 0..3, a null required pointer, clone_max_scale <= 0, min_opacity outside
+ * [0, 1) or a NaN threshold; GSR_ERR_WORKSPACE_TOO_SMALL; GSR_ERR_HIP. */
+gsr_status gsr_densify_count(int64_t n, int32_t sh_degree, const gsr_densify_opts *opts, const gsr_gaussians *g,
+                             const gsr_stats *stats, const uint8_t *in_block, void *ws, size_t ws_bytes,
+                             void *stream, int64_t *n_out);
+
+/* Second half: writes the n_out outputs counted by gsr_densify_count, whose
+ * workspace and inputs it must be given unchanged, on the same stream.
+ * out: writable device planes of n_out Gaussians (gsr_grads layout: means
+ * [3][n_out], log_scales, quats, opacity_logits, sh [3K][n_out]).  m_in /
+ * v_in and m_out / v_out (Adam moments, same layouts over n and n_out) are
+ * optional together (NULL: no moments); parent_out (device [n_out] int64,
+ * optional) receives each output's input index.  samples: device
+ * [2][3][n] float.  Outputs beyond n_out are never written.  The caller
+ * resets the statistics afterwards.  Errors as gsr_densify_count. */
+gsr_status gsr_densify_apply(int64_t n, int32_t sh_degree, const gsr_densify_opts *opts, const gsr_gaussians *g,
+                             const gsr_grads *m_in, const gsr_grads *v_in, const gsr_stats *stats,
+                             const uint8_t *in_block, const float *samples, int64_t n_out, const gsr_grads *out,
+                             const gsr_grads *m_out, const gsr_grads *v_out, int64_t *parent_out, void *ws,
+                             size_t ws_bytes, void *stream);
+
 /* ---- Optimizer step (the NEXT stage after the reverse projection) ------
  * The paper locates the cost of Gaussians that no assigned camera sees in the
  * optimizer rather than in rendering (Sec. 3.3) and uses Sparse Adam in the

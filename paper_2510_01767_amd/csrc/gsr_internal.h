@@ -144,6 +144,29 @@ int launch_adam(const KAdam &a, int planes, void *stream);
 
 // Fast camera selection (gsr_fcs.hip): back-projected depth pixels counted
 // per (view, block) box, the ratio to the view's pixel count and tau.
+// Densification: inputs, decision thresholds and outputs.
+struct KDensify {
+  const float *mean, *ls, *quat, *opa, *sh;
+  const uint8_t *keep;
+  const float *m[5], *v[5];  // moments in, by group (means, log_scales, quats, opacity, sh)
+  const float *S;
+  const uint32_t *cnt;
+  const uint8_t *in_block;
+  const float *samples;  // [2][3][n]
+  int64_t n, n_out;
+  int sh_planes;
+  int opa_on, world_on, selective;
+  double grad_thr, log_clone_max, logit_min, log_world_max;
+  float child_dlog;  // ln(1.6) rounded to float
+  float *o_mean, *o_ls, *o_quat, *o_opa, *o_sh;
+  float *om[5], *ov[5];
+  int64_t *parent;
+  uint64_t *block_sums;  // [blocks + 1]
+};
+int64_t densify_blocks(int64_t n);
+int launch_densify_count(const KDensify &k, void *stream);
+int launch_densify_apply(const KDensify &k, void *stream);
+
 // Device workspace of the partition's pixel counting: the selected views'
 // pixel ranges, the candidate boxes and their counts.
 struct PartitionView {

@@ -68,6 +68,11 @@ class gsr_stats(ctypes.Structure):
     _fields_ = [("grad2d_norm_sum", _vp), ("visible_count", _vp)]
 
 
+class gsr_densify_opts(ctypes.Structure):
+    _fields_ = [("grad_threshold", _f32), ("clone_max_scale", _f32), ("min_opacity", _f32),
+                ("max_world_scale", _f32), ("selective", _i32), ("reserved", _i32)]
+
+
 class gsr_counts(ctypes.Structure):
     _fields_ = [("visible", _i64 * GSR_MAX_VIEWS), ("intersections", _i64 * GSR_MAX_VIEWS),
                 ("visible_total", _i64), ("intersections_total", _i64), ("visible_union", _i64),
@@ -100,6 +105,7 @@ class gsr_adam(ctypes.Structure):
 EXPORTS = (
     "gsr_last_stage_times", "gsr_adam_step", "gsr_render_depth", "gsr_camera_coverage", "gsr_back_project",
     "gsr_partition_blocks", "gsr_partition_workspace_size", "gsr_partition_blocks_device",
+    "gsr_densify_workspace_size", "gsr_densify_count", "gsr_densify_apply",
     "gsr_default_options", "gsr_plan_create", "gsr_plan_destroy", "gsr_workspace_size",
     "gsr_workspace_layout", "gsr_image_offset", "gsr_forward", "gsr_backward",
     "gsr_forward_backward_l1", "gsr_visibility_mask", "gsr_graph_capture", "gsr_graph_launch",
@@ -147,6 +153,12 @@ def load(build_if_missing: bool = True):
     L.gsr_partition_workspace_size.argtypes = [_i32, P(_sz)]
     L.gsr_partition_blocks_device.argtypes = [P(_f32), P(_f32), _i64, _vp, P(_i64), _i32, _i32, _f32, _i32, _f32,
                                               _f32, _vp, _sz, _vp, P(_f32), P(ctypes.c_uint8), P(_i32)]
+    L.gsr_densify_workspace_size.argtypes = [_i64, P(_sz)]
+    L.gsr_densify_count.argtypes = [_i64, _i32, P(gsr_densify_opts), P(gsr_gaussians), P(gsr_stats), _vp, _vp, _sz,
+                                    _vp, P(_i64)]
+    L.gsr_densify_apply.argtypes = [_i64, _i32, P(gsr_densify_opts), P(gsr_gaussians), P(gsr_grads), P(gsr_grads),
+                                    P(gsr_stats), _vp, _vp, _i64, P(gsr_grads), P(gsr_grads), P(gsr_grads), _vp,
+                                    _vp, _sz, _vp]
     L.gsr_render_depth.argtypes = [_vp, P(gsr_gaussians), _vp, _vp, _vp, _vp, _sz, _vp]
     L.gsr_camera_coverage.argtypes = [_vp, _vp, _vp, _vp, _i32, _f32, _vp, _vp, _vp, _vp]
     L.gsr_adam_step.argtypes = [_vp, P(gsr_adam), P(gsr_grads), P(gsr_grads), P(gsr_grads), P(gsr_grads), _vp,
@@ -292,6 +304,28 @@ def gsr_partition_blocks_device(scene_aabb, centers, points_ptr, view_offsets, n
                                               ws_bytes, stream, _ptr(blocks, _f32), _ptr(assign, ctypes.c_uint8),
                                               _ptr(work, _i32)), None)
     return blocks, assign, work
+
+
+def gsr_densify_workspace_size(n):
+    out = _sz(0)
+    _check(load().gsr_densify_workspace_size(n, ctypes.byref(out)), None)
+    return out.value
+
+
+def gsr_densify_count(n, sh_degree, opts, g, stats, in_block, ws, ws_bytes, stream):
+    """Returns the output count (synchronizes the stream)."""
+    out = _i64(0)
+    _check(load().gsr_densify_count(n, sh_degree, ctypes.byref(opts), ctypes.byref(g), ctypes.byref(stats), in_block,
+                                    ws, ws_bytes, stream, ctypes.byref(out)), None)
+    return out.value
+
+
+def gsr_densify_apply(n, sh_degree, opts, g, m_in, v_in, stats, in_block, samples, n_out, out, m_out, v_out,
+                      parent_out, ws, ws_bytes, stream):
+    ref = lambda x: ctypes.byref(x) if x is not None else None
+    _check(load().gsr_densify_apply(n, sh_degree, ctypes.byref(opts), ctypes.byref(g), ref(m_in), ref(v_in),
+                                    ctypes.byref(stats), in_block, samples, n_out, ref(out), ref(m_out), ref(v_out),
+                                    parent_out, ws, ws_bytes, stream), None)
 
 
 def gsr_adam_step(plan, hp, params, grads, m, v, visible_bits, stream):

@@ -57,6 +57,34 @@ def partition_blocks_device(scene_aabb, centers, points, view_offsets, n_blocks,
                                          ws.data_ptr(), ws_bytes, s.cuda_stream, tau, refine_steps, q_min, q_max)
 
 
+def densify(params, S, count, samples, grad_threshold, clone_max_scale, min_opacity=0.0, max_world_scale=0.0,
+            in_block=None, keep=None, m=None, v=None, stream=None):
+    """gsr_densify_count + gsr_densify_apply on dicts of CUDA planes (PARAM_NAMES keys).
+    Selective densification when in_block (uint8 [n]) is given.  Returns (params, m, v, parent)
+    with m / v None unless given."""
+    n = params["opacity_logits"].shape[-1]
+    sh_degree = int(round((params["sh"].shape[0] // 3) ** 0.5)) - 1
+    dev = params["means"].device
+    opts = C.gsr_densify_opts(grad_threshold, clone_max_scale, min_opacity, max_world_scale,
+                              1 if in_block is not None else 0, 0)
+    g = Rasterizer.gaussians(params, keep)
+    stats = C.gsr_stats(S.data_ptr(), count.data_ptr())
+    ws_bytes = C.gsr_densify_workspace_size(n)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    s = (torch.cuda.current_stream(dev) if stream is None else stream).cuda_stream
+    blk = in_block.data_ptr() if in_block is not None else None
+    n_out = C.gsr_densify_count(n, sh_degree, opts, g, stats, blk, ws.data_ptr(), ws_bytes, s)
+    new = lambda: {k: torch.empty((params[k].shape[0], n_out) if params[k].dim() == 2 else (n_out,),
+                                  dtype=torch.float32, device=dev) for k in PARAM_NAMES}
+    out = new()
+    mo, vo = (new(), new()) if m is not None else (None, None)
+    parent = torch.empty(n_out, dtype=torch.int64, device=dev)
+    gs = lambda d: C.gsr_grads(*[d[k].data_ptr() for k in PARAM_NAMES]) if d is not None else None
+    C.gsr_densify_apply(n, sh_degree, opts, g, gs(m), gs(v), stats, blk, samples.data_ptr(), n_out, gs(out),
+                        gs(mo), gs(vo), parent.data_ptr(), ws.data_ptr(), ws_bytes, s)
+    return out, mo, vo, parent
+
+
 class Rasterizer:
     """One plan + workspace for a fixed problem shape."""
 

@@ -1,0 +1,120 @@
+"""GPU parity of selective densification and pruning (gsr_densify_count /
+gsr_densify_apply) against the oracle on the same float32 inputs and normal
+draws: the output count and every output's parent exactly; copied planes,
+the children's log scales and the moments bit for bit; the children's means
+(float64 arithmetic rounded once to float32) within one float32 ulp."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import densify as od
+from paper_2510_01767_amd import scenes
+from paper_2510_01767_amd.raster import PARAM_NAMES, densify, scene_tensors
+
+pytestmark = pytest.mark.gpu
+f32 = np.float32
+
+
+def announce(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def make_inputs(n, sh_degree, seed):
+    rng = np.random.default_rng(seed)
+    K = (sh_degree + 1) ** 2
+    P = dict(means=rng.uniform(-10, 10, (3, n)).astype(f32), log_scales=rng.normal(-3.0, 1.0, (3, n)).astype(f32),
+             quats=rng.normal(size=(4, n)).astype(f32), opacity_logits=rng.normal(0, 3, n).astype(f32),
+             sh=rng.normal(size=(3 * K, n)).astype(f32))
+    S = (rng.exponential(0.5, n) * rng.integers(0, 2, n)).astype(f32)
+    cnt = rng.integers(0, 6, n).astype(np.uint32)
+    in_block = np.all(np.abs(P["means"]) < 6, axis=0).astype(np.uint8)
+    keep = (rng.uniform(size=n) > 0.1).astype(np.uint8)
+    samples = rng.standard_normal((2, 3, n)).astype(f32)
+    m = {g: rng.normal(size=P[g].shape).astype(f32) for g in od.GROUPS}
+    v = {g: rng.uniform(size=P[g].shape).astype(f32) for g in od.GROUPS}
+    return P, S, cnt, in_block, keep, samples, m, v
+
+
+def cuda(d):
+    return {k: torch.from_numpy(np.ascontiguousarray(x)).cuda() for k, x in d.items()}
+
+
+def run_both(P, S, cnt, in_block, keep, samples, m, v, thr, clone_max, min_opacity, max_world, selective,
+             use_keep, use_moments):
+    ora = od.densify_prune(P, S, cnt, in_block, samples, thr, clone_max, min_opacity, max_world, selective,
+                           keep if use_keep else None, m if use_moments else None, v if use_moments else None)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out, mo, vo, parent = densify(cuda(P), t(S), t(cnt.view(np.int32)), t(samples), thr, clone_max, min_opacity,
+                                  max_world, in_block=t(in_block) if selective else None,
+                                  keep=t(keep) if use_keep else None, m=cuda(m) if use_moments else None,
+                                  v=cuda(v) if use_moments else None)
+    torch.cuda.synchronize()
+    return ora, {k: x.cpu().numpy() for k, x in out.items()}, mo, vo, parent.cpu().numpy()
+
+
+def compare(ora, out, mo, vo, parent):
+    assert np.array_equal(parent, ora["parent"])
+    o = ora["params"]
+    child = np.zeros(len(parent), bool)
+    child[:] = (ora["kind"][parent] == 2)
+    for g in ("quats", "opacity_logits", "sh"):
+        assert np.array_equal(out[g], o[g]), g
+    assert np.array_equal(out["log_scales"], o["log_scales"])
+    assert np.array_equal(out["means"][:, ~child], o["means"][:, ~child].astype(f32))
+    ref = o["means"][:, child]
+    ulp = np.spacing(np.abs(ref).astype(f32)).astype(np.float64)
+    assert np.all(np.abs(out["means"][:, child] - ref) <= ulp)
+    if ora["m"] is not None:
+        for g in od.GROUPS:
+            assert np.array_equal(mo[g].cpu().numpy(), ora["m"][g]), g
+            assert np.array_equal(vo[g].cpu().numpy(), ora["v"][g]), g
+
+
+CASES = [  # thr, clone_max, min_opacity, max_world, selective, keep, moments
+    (0.4, 0.05, 0.005, 0.0, True, False, True),
+    (0.4, 0.05, 0.0, 0.0, False, False, False),
+    (0.2, 0.02, 0.01, 0.3, True, True, True),
+    (np.inf, 0.05, 0.0, 0.0, True, True, False),
+    (0.0, 1e-6, 0.0, 0.0, False, False, True),  # every seen Gaussian splits
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_densify_matches_the_oracle(case):
+    thr, cm, mo_, mw, sel, use_keep, use_m = CASES[case]
+    announce("densify", case, CASES[case])
+    inputs = make_inputs(9_999, 3 if case % 2 == 0 else 1, scenes.SEED_BASE + 600 + case)
+    ora, out, mo, vo, parent = run_both(*inputs, thr, cm, mo_, mw, sel, use_keep, use_m)
+    compare(ora, out, mo, vo, parent)
+    print("outputs", len(parent), "kinds", np.bincount(ora["kind"], minlength=3).tolist(), flush=True)
+
+
+def test_densify_edge_sizes():
+    for n in (1, 2, 1023, 1024, 1025, 4097):
+        announce("densify edge", n)
+        inputs = make_inputs(n, 0, scenes.SEED_BASE + 650 + n)
+        ora, out, mo, vo, parent = run_both(*inputs, 0.3, 0.05, 0.005, 0.0, True, True, True)
+        compare(ora, out, mo, vo, parent)
+    # everything pruned: no outputs
+    announce("densify all pruned")
+    P, S, cnt, blk, keep, samples, m, v = make_inputs(3000, 0, 7)
+    ora, out, mo, vo, parent = run_both(P, S, cnt, blk, np.zeros_like(keep), samples, m, v, 0.3, 0.05, 0.0, 0.0,
+                                        True, True, False)
+    assert len(parent) == 0 and len(ora["parent"]) == 0
+
+
+@pytest.mark.timeout(600)
+def test_densify_at_the_bench_workload():
+    s = scenes.config2()
+    announce("densify config2", s.n)
+    rng = np.random.default_rng(scenes.SEED_BASE + 660)
+    P = {k: getattr(s, k) for k in PARAM_NAMES}
+    S = (rng.exponential(2e-4, s.n) * 16).astype(f32)
+    cnt = rng.integers(0, 17, s.n).astype(np.uint32)
+    aabb = s.block_aabb
+    in_block = np.all((s.means >= aabb[:3, None]) & (s.means < aabb[3:, None]), axis=0).astype(np.uint8)
+    samples = rng.standard_normal((2, 3, s.n)).astype(f32)
+    ora, out, mo, vo, parent = run_both(P, S, cnt, in_block, None, samples, None, None, 2e-4, 0.01 * 200.0,
+                                        0.005, 0.0, True, False, False)
+    compare(ora, out, mo, vo, parent)
+    print("outputs", len(parent), "kinds", np.bincount(ora["kind"], minlength=3).tolist(), flush=True)
