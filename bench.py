@@ -81,6 +81,7 @@ def main():
     ap.add_argument("--no-adam", action="store_true")
     ap.add_argument("--no-fcs", action="store_true")
     ap.add_argument("--no-partition", action="store_true")
+    ap.add_argument("--no-densify", action="store_true")
     ap.add_argument("--tile", default=None, help="fixed tile shape WxH (with --no-autotune)")
     ap.add_argument("--lds-batch", type=int, default=256, help="with --no-autotune")
     ap.add_argument("--grid-per-cu", type=int, default=8, help="with --no-autotune")
@@ -131,7 +132,7 @@ def main():
     tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else (8, 32)
     rb = Rasterizer(scene.n, scene.sh_degree, sizes, mode="batched", tile=tile, profile_stages=1,
                     lds_batch=args.lds_batch, grid_per_cu=args.grid_per_cu, bwd_reduce=args.bwd_reduce)
-    rb.step_l1(params, cams, targets, stats=False)
+    rb.step_l1(params, cams, targets, stats=True)
     counts = rb.counts()
     log(f"visible {counts.visible_total}, union {counts.visible_union}, intersections "
         f"{counts.intersections_total}, capacity {rb.layout.capacity}")
@@ -144,7 +145,7 @@ def main():
     # ---- timed region: K replays of the captured batched step
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        rb.capture(params, cams, targets, stats=False)
+        rb.capture(params, cams, targets, stats=True)
     stream.synchronize()
     for _ in range(args.warmup):
         rb.launch(stream=stream)
@@ -175,7 +176,7 @@ def main():
     stage_tot = {}
     with torch.cuda.stream(stream):
         for _ in range(args.steps):
-            rb.step_l1(params, cams, targets, stats=False, stream=stream)
+            rb.step_l1(params, cams, targets, stats=True, stream=stream)
             for name, (ms, k) in C.gsr_last_stage_times(rb.plan).items():
                 a = stage_tot.setdefault(name, [0.0, 0])
                 a[0] += ms
@@ -189,11 +190,11 @@ def main():
     ms_plain = None
     if not args.no_plain:
         rp = Rasterizer(scene.n, scene.sh_degree, sizes, mode="plain", tile=(16, 16))
-        rp.step_l1(params, cams, targets, stats=False)
+        rp.step_l1(params, cams, targets, stats=True)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         for _ in range(args.plain_steps):
-            rp.step_l1(params, cams, targets, stats=False)
+            rp.step_l1(params, cams, targets, stats=True)
         torch.cuda.synchronize()
         ms_plain = 1000 * (time.perf_counter() - w0) / args.plain_steps
         log(f"plain per-view step {ms_plain:.3f} ms")
@@ -206,7 +207,7 @@ def main():
         rr = Rasterizer(scene.n, scene.sh_degree, sizes, mode="batched", tile=(opt.tile_w, opt.tile_h),
                         lds_batch=opt.lds_batch, grid_per_cu=opt.grid_per_cu, bwd_reduce=opt.bwd_reduce)
         with torch.cuda.stream(stream):
-            rr.capture(pr, cams, targets, stats=False)
+            rr.capture(pr, cams, targets, stats=True)
         stream.synchronize()
         for _ in range(args.warmup):
             rr.launch(stream=stream)
@@ -228,7 +229,7 @@ def main():
         ma = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
         va = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
         lr = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3, 1.25e-4)
-        rb.step_l1(params, cams, targets, stats=False, stream=stream)
+        rb.step_l1(params, cams, targets, stats=True, stream=stream)
         res = {}
         for name, vis in (("dense", False), ("visible_only", True)):
             rb.adam_step(pa, rb.grads, ma, va, lr, 1, visible_only=vis, stream=stream)
@@ -250,6 +251,75 @@ def main():
                 "visible_only_GBps": round(b_vis / (res["visible_only"] * 1e-3) / 1e9, 1)}
         log(f"adam: {adam}")
         del pa, ma, va
+
+    # ---- selective densification on the statistics of one step over the 16 views: threshold at
+    # the 90th percentile of S / n, clone / split cut at the median largest scale, in-block only
+    dens = None
+    if not args.no_densify:
+        from paper_2510_01767_amd.raster import PARAM_NAMES
+        n = scene.n
+        rb.S.zero_()
+        rb.count.zero_()
+        rb.step_l1(params, cams, targets, stats=True, stream=stream)
+        torch.cuda.synchronize()
+        seen = rb.count > 0
+        thr = float(torch.quantile((rb.S[seen] / rb.count[seen].float())[: 1 << 24], 0.9))
+        cut = float(torch.exp(params["log_scales"].max(dim=0).values).median())
+        aabb = torch.from_numpy(np.asarray(scene.block_aabb, np.float32)).cuda()
+        in_block = ((params["means"] >= aabb[:3, None]) & (params["means"] < aabb[3:, None])).all(0)
+        in_block = in_block.to(torch.uint8).contiguous()
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(20251001)
+        samples = torch.randn((2, 3, n), generator=gen, device="cuda")
+        md = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+        vd = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+        opts_d = C.gsr_densify_opts(thr, cut, 0.005, 0.0, 1, 0)
+        g_in = rb.gaussians(params)
+        st = C.gsr_stats(rb.S.data_ptr(), rb.count.data_ptr())
+        wsb = C.gsr_densify_workspace_size(n)
+        wsd = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        sh_ = stream.cuda_stream
+        count = lambda: C.gsr_densify_count(n, scene.sh_degree, opts_d, g_in, st, in_block.data_ptr(),
+                                            wsd.data_ptr(), wsb, sh_)
+        n_out = count()
+        walls = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            count()
+            walls.append((time.perf_counter() - t0) * 1e3)
+        new = lambda: {k: torch.empty((params[k].shape[0], n_out) if params[k].dim() == 2 else (n_out,),
+                                      dtype=torch.float32, device="cuda") for k in PARAM_NAMES}
+        out, mo, vo = new(), new(), new()
+        parent = torch.empty(n_out, dtype=torch.int64, device="cuda")
+        gs = lambda d: C.gsr_grads(*[d[k].data_ptr() for k in PARAM_NAMES])
+        apply = lambda: C.gsr_densify_apply(n, scene.sh_degree, opts_d, g_in, gs(md), gs(vd), st,
+                                            in_block.data_ptr(), samples.data_ptr(), n_out, gs(out), gs(mo),
+                                            gs(vo), parent.data_ptr(), wsd.data_ptr(), wsb, sh_)
+        apply()
+        d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        d0.record(stream)
+        for _ in range(args.steps):
+            apply()
+        d1.record(stream)
+        torch.cuda.synchronize()
+        ms_apply = d0.elapsed_time(d1) / args.steps
+        # algorithmic bytes of the apply kernel: the decision inputs of every Gaussian (25 B),
+        # the 59 planes (236 B) of every producing Gaussian plus its moments (472 B) or, for a
+        # split, its 6 normal draws (24 B); per output 236 B of planes, 472 B of moments, 8 B
+        # of parent index
+        P = 4 * (11 + 3 * (scene.sh_degree + 1) ** 2)
+        producing = torch.unique(parent).numel()
+        child = (out["means"] != params["means"][:, parent]).any(0)
+        n_split = int(child.sum().item()) // 2
+        b_alg = (25 * n + producing * P + (producing - n_split) * 2 * P + n_split * 24 + n_out * (3 * P + 8))
+        gbs = b_alg / (ms_apply * 1e-3) / 1e9
+        dens = {"gaussians_in": n, "gaussians_out": n_out, "splits": n_split,
+                "clones": n_out - producing - n_split, "grad_threshold": thr, "clone_max_scale": cut,
+                "count_ms_wall": round(min(walls), 4), "apply_ms": round(ms_apply, 4), "bytes_apply": b_alg,
+                "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+        log(f"densify: {dens}")
+        del out, mo, vo, md, vd, samples, parent
 
     # ---- fast camera selection: one depth-compositing pass over the views, then the
     # back-projected pixels counted into a 4 x 4 grid of blocks over the scene
@@ -396,7 +466,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": scene_random.name, "gaussians": n, "views": V, "pixels": P,
-                   "form": "batched fused fwd+L1+bwd, one HIP graph",
+                   "form": "batched fused fwd+L1+bwd with SD statistics, one HIP graph",
                    "tile": f"{opt.tile_w}x{opt.tile_h}", "lds_batch": opt.lds_batch,
                    "grid_per_cu": opt.grid_per_cu, "bwd_variant": "stored" if counts.bwd_variant == 2 else "recompute",
                    "gaussian_order": args.order},
@@ -411,6 +481,7 @@ def main():
         "roofline": roof,
         "adam": adam,
         "fcs": fcs,
+        "densify": dens,
         "parity": parity,
         "cpu_baseline": cpu,
     }

@@ -19,6 +19,7 @@ namespace {
 
 constexpr int kItems = 4;                       // consecutive Gaussians per thread
 constexpr int kChunk = kBlock * kItems;         // Gaussians per workgroup
+constexpr int kPlaneSplit = 4;                  // workgroups sharing a chunk's planes
 
 struct Decision {
   int kind;  // 0 keep, 1 clone, 2 split
@@ -110,85 +111,137 @@ __global__ __launch_bounds__(1024) void k_densify_scan(uint64_t *sums, int64_t n
   if (threadIdx.x == 0) sums[nb] = carry;
 }
 
-__device__ __forceinline__ void copy_planes(const float *src, float *dst, int planes, int64_t n, int64_t n_out,
-                                            int64_t i, int64_t pos) {
-  for (int p = 0; p < planes; p++) dst[p * n_out + pos] = src[p * n + i];
-}
-
-__device__ __forceinline__ void zero_planes(float *dst, int planes, int64_t n_out, int64_t pos) {
-  for (int p = 0; p < planes; p++) dst[p * n_out + pos] = 0.0f;
-}
-
-// one output of Gaussian i at pos; child = -1 for a copy, else the child
-// index of a split
-__device__ void write_output(const KDensify &k, int64_t i, int64_t pos, int child, bool moments) {
+// The two children's means of split Gaussian i at pos, pos + 1:
+// mean + R(q / |q|) (exp(log_scale) * eps_j), in double, rounded once.
+__device__ void child_means(const KDensify &k, int64_t i, int64_t pos) {
   const int64_t n = k.n, no = k.n_out;
-  if (child < 0) {
-    copy_planes(k.mean, k.o_mean, 3, n, no, i, pos);
-    copy_planes(k.ls, k.o_ls, 3, n, no, i, pos);
-  } else {
-    // mean + R(q / |q|) (s * eps), s = exp(log_scale), in double
-    const double qw = k.quat[i], qx = k.quat[n + i], qy = k.quat[2 * n + i], qz = k.quat[3 * n + i];
-    const double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-    const double w = qw * inv, x = qx * inv, y = qy * inv, z = qz * inv;
-    const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z),     2 * (x * z + w * y),
-                         2 * (x * y + w * z),     1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
-                         2 * (x * z - w * y),     2 * (y * z + w * x),     1 - 2 * (x * x + y * y)};
+  const double qw = k.quat[i], qx = k.quat[n + i], qy = k.quat[2 * n + i], qz = k.quat[3 * n + i];
+  const double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  const double w = qw * inv, x = qx * inv, y = qy * inv, z = qz * inv;
+  const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z),     2 * (x * z + w * y),
+                       2 * (x * y + w * z),     1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                       2 * (x * z - w * y),     2 * (y * z + w * x),     1 - 2 * (x * x + y * y)};
+  const double s[3] = {exp((double)k.ls[i]), exp((double)k.ls[n + i]), exp((double)k.ls[2 * n + i])};
+  for (int j = 0; j < 2; j++) {
     double d[3];
 #pragma unroll
-    for (int a = 0; a < 3; a++)
-      d[a] = exp((double)k.ls[a * n + i]) * (double)k.samples[(int64_t)(child * 3 + a) * n + i];
+    for (int a = 0; a < 3; a++) d[a] = s[a] * (double)k.samples[(int64_t)(j * 3 + a) * n + i];
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-      k.o_mean[a * no + pos] = (float)((double)k.mean[a * n + i] + R[3 * a] * d[0] + R[3 * a + 1] * d[1] +
-                                       R[3 * a + 2] * d[2]);
-      k.o_ls[a * no + pos] = k.ls[a * n + i] - k.child_dlog;
-    }
+    for (int a = 0; a < 3; a++)
+      k.o_mean[a * no + pos + j] =
+          (float)((double)k.mean[a * n + i] + R[3 * a] * d[0] + R[3 * a + 1] * d[1] + R[3 * a + 2] * d[2]);
   }
-  copy_planes(k.quat, k.o_quat, 4, n, no, i, pos);
-  k.o_opa[pos] = k.opa[i];
-  copy_planes(k.sh, k.o_sh, k.sh_planes, n, no, i, pos);
-  if (k.parent) k.parent[pos] = i;
-  const int planes[5] = {3, 3, 4, 1, k.sh_planes};
-  for (int g = 0; g < 5; g++) {
-    if (k.om[g]) {
-      if (moments) copy_planes(k.m[g], k.om[g], planes[g], n, no, i, pos);
-      else zero_planes(k.om[g], planes[g], no, pos);
-    }
-    if (k.ov[g]) {
-      if (moments) copy_planes(k.v[g], k.ov[g], planes[g], n, no, i, pos);
-      else zero_planes(k.ov[g], planes[g], no, pos);
+}
+
+enum PlaneMode { kMeans, kLogScales, kCopied, kMoments };
+
+// One plane of the block's Gaussians: consecutive lanes read consecutive
+// Gaussians and write their outputs, which are consecutive too; the
+// kItems loads of a thread are issued before its stores.  dec / pos: the
+// thread's Gaussians (threadIdx.x + r kBlock), c = 0 for none.
+template <int MODE>
+__device__ __forceinline__ void copy_plane(const KDensify &k, const int *dec, const int64_t *pos, const float *src,
+                                           float *dst) {
+  float v[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; r++) {
+    const bool load = (dec[r] & 3) != 0 && !(MODE == kMoments && (dec[r] >> 2) == 2);
+    v[r] = load ? src[threadIdx.x + r * kBlock] : 0.0f;
+  }
+#pragma unroll
+  for (int r = 0; r < kItems; r++) {
+    const int c = dec[r] & 3, kind = dec[r] >> 2;
+    if (c == 0) continue;
+    if (MODE == kMoments) {
+      dst[pos[r]] = v[r];
+      if (c == 2) dst[pos[r] + 1] = 0.0f;  // a clone or a child starts from zero moments
+    } else if (MODE == kMeans) {
+      if (kind == 2) continue;  // the children's means are written apart
+      dst[pos[r]] = v[r];
+      if (c == 2) dst[pos[r] + 1] = v[r];
+    } else {
+      const float x = (MODE == kLogScales && kind == 2) ? v[r] - k.child_dlog : v[r];
+      dst[pos[r]] = x;
+      if (c == 2) dst[pos[r] + 1] = x;
     }
   }
 }
 
+// Decisions and block-local offsets first (kItems consecutive Gaussians per
+// thread, as in the count), kept in LDS; then plane by plane, each plane of
+// the block's Gaussians read and written in contiguous runs.
 __global__ __launch_bounds__(kBlock) void k_densify_apply(KDensify k) {
   __shared__ uint64_t s_tmp[kBlock / 64];
-  const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
-  Decision d[kItems];
+  __shared__ uint16_t s_off[kChunk];  // block-local output offset (< 2 kChunk)
+  __shared__ uint8_t s_dec[kChunk];   // kind * 4 + c
+  const int64_t first = (int64_t)blockIdx.x * kChunk;
+  const int64_t base = first + (int64_t)threadIdx.x * kItems;
+  uint8_t dec[kItems];
   uint64_t sum = 0;
 #pragma unroll
   for (int j = 0; j < kItems; j++) {
-    d[j] = base + j < k.n ? decide(k, base + j) : Decision{0, 0};
-    sum += (uint64_t)d[j].c;
+    const Decision d = base + j < k.n ? decide(k, base + j) : Decision{0, 0};
+    dec[j] = (uint8_t)(d.kind * 4 + d.c);
+    sum += (uint64_t)d.c;
   }
   uint64_t total;
-  uint64_t pos = k.block_sums[blockIdx.x] + block_exclusive_sum(sum, s_tmp, &total);
+  uint64_t off = block_exclusive_sum(sum, s_tmp, &total);
 #pragma unroll
   for (int j = 0; j < kItems; j++) {
-    const int64_t i = base + j;
-    if (d[j].c == 0) continue;
-    if ((int64_t)pos + d[j].c > k.n_out) return;  // fewer outputs than counted: the caller's n_out is short
-    if (d[j].kind == 0) {
-      write_output(k, i, (int64_t)pos, -1, true);
-    } else if (d[j].kind == 1) {
-      write_output(k, i, (int64_t)pos, -1, true);       // the original keeps its optimizer state
-      write_output(k, i, (int64_t)pos + 1, -1, false);  // the clone starts from zero moments
-    } else {
-      write_output(k, i, (int64_t)pos, 0, false);
-      write_output(k, i, (int64_t)pos + 1, 1, false);
+    s_off[threadIdx.x * kItems + j] = (uint16_t)off;
+    s_dec[threadIdx.x * kItems + j] = dec[j];
+    off += dec[j] & 3;
+  }
+  __syncthreads();
+  const int64_t bp = (int64_t)k.block_sums[blockIdx.x];
+  const int count = (int)min((int64_t)kChunk, k.n - first);
+  const int64_t n = k.n, no = k.n_out;
+  // this thread's Gaussians for every plane, from LDS once
+  int mdec[kItems];
+  int64_t mpos[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; r++) {
+    const int t = threadIdx.x + r * kBlock;
+    mdec[r] = t < count ? s_dec[t] : 0;
+    mpos[r] = t < count ? bp + s_off[t] : 0;
+    if (mpos[r] + (mdec[r] & 3) > no) mdec[r] = 0;  // fewer outputs than counted: the caller's n_out is short
+  }
+  if (blockIdx.y == 0) {
+#pragma unroll
+    for (int r = 0; r < kItems; r++) {
+      const int c = mdec[r] & 3;
+      const int64_t i = first + threadIdx.x + r * kBlock;
+      if (c == 0) continue;
+      if ((mdec[r] >> 2) == 2) child_means(k, i, mpos[r]);  // split Gaussians (a minority)
+      if (k.parent) {
+        k.parent[mpos[r]] = i;
+        if (c == 2) k.parent[mpos[r] + 1] = i;
+      }
     }
-    pos += d[j].c;
+  }
+  // the planes, spread over gridDim.y workgroups per chunk: 11 + SH planes of
+  // parameters, then the same planes of each moment when present
+  const int P = 11 + k.sh_planes;
+  const int Q = k.om[0] ? 3 * P : P;
+  for (int q = blockIdx.y; q < Q; q += gridDim.y) {
+    const int which = q / P, r = q % P;  // 0 parameters, 1 first moments, 2 second moments
+    if (which > 0) {
+      const int g = r < 3 ? 0 : r < 6 ? 1 : r < 10 ? 2 : r < 11 ? 3 : 4;
+      const int p = r - (g == 0 ? 0 : g == 1 ? 3 : g == 2 ? 6 : g == 3 ? 10 : 11);
+      const float *src = (which == 1 ? k.m[g] : k.v[g]) + p * n + first;
+      float *dst = (which == 1 ? k.om[g] : k.ov[g]) + p * no;
+      copy_plane<kMoments>(k, mdec, mpos, src, dst);
+    } else if (r < 3) {
+      copy_plane<kMeans>(k, mdec, mpos, k.mean + r * n + first, k.o_mean + r * no);
+    } else if (r < 6) {
+      copy_plane<kLogScales>(k, mdec, mpos, k.ls + (r - 3) * n + first, k.o_ls + (r - 3) * no);
+    } else if (r < 10) {
+      copy_plane<kCopied>(k, mdec, mpos, k.quat + (r - 6) * n + first, k.o_quat + (r - 6) * no);
+    } else if (r < 11) {
+      copy_plane<kCopied>(k, mdec, mpos, k.opa + first, k.o_opa);
+    } else {
+      copy_plane<kCopied>(k, mdec, mpos, k.sh + (r - 11) * n + first, k.o_sh + (r - 11) * no);
+    }
   }
 }
 
@@ -206,7 +259,10 @@ int launch_densify_count(const KDensify &k, void *stream) {
 
 int launch_densify_apply(const KDensify &k, void *stream) {
   const int64_t nb = densify_blocks(k.n);
-  if (nb > 0) hipLaunchKernelGGL(k_densify_apply, dim3((unsigned)nb), dim3(kBlock), 0, (hipStream_t)stream, k);
+  // each chunk's planes over kPlaneSplit workgroups: more loads in flight, at
+  // the price of deciding each Gaussian kPlaneSplit times
+  if (nb > 0)
+    hipLaunchKernelGGL(k_densify_apply, dim3((unsigned)nb, kPlaneSplit), dim3(kBlock), 0, (hipStream_t)stream, k);
   return last_err();
 }
 
