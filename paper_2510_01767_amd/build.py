@@ -14,7 +14,7 @@ SOURCES = [os.path.join(CSRC, "gsr_api.cpp"), os.path.join(CSRC, "gsr_kernels.hi
            os.path.join(CSRC, "gsr_fcs.hip"), os.path.join(CSRC, "gsr_partition.cpp"),
            os.path.join(CSRC, "gsr_densify.hip")]
 HEADERS = [os.path.join(ROOT, "include", "gsr.h"), os.path.join(CSRC, "gsr_internal.h"),
-           os.path.join(CSRC, "gsr_device.h")]
+           os.path.join(CSRC, "gsr_device.h"), os.path.join(CSRC, "gsr_stages.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "gsr_internal.h"
+#include "gsr_stages.h"
 
 struct gsr_plan {
   gsr_problem prob;

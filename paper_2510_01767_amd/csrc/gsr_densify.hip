@@ -12,6 +12,7 @@
 #include <cmath>
 
 #include "gsr_device.h"
+#include "gsr_stages.h"
 
 namespace gsr {
 

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include "gsr_device.h"
+#include "gsr_stages.h"
 
 namespace gsr {
 

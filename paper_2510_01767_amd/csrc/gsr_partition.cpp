@@ -24,6 +24,7 @@
 
 #include "gsr.h"
 #include "gsr_internal.h"
+#include "gsr_stages.h"
 
 namespace {
 
