@@ -145,30 +145,52 @@ __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera 
       tmax = max(tmax, __shfl_xor(tmax, m));
     }
     const bool gather = tmax - tmin <= 2 * vi.tiles_x + 2;
-    uint32_t rk[4] = {0u, 0u, 0u, 0u};
+    // Group the lanes that share a tile (per rank slot q) with ballots only:
+    // which group no atomic result decides, so the groups are formed first,
+    // each group's lowest lane then takes one atomic for the group, and all
+    // of a lane's atomics are in flight together.  Lanes left after the
+    // rounds, or all lanes when the wavefront is spread out, form groups of
+    // one.
+    int32_t tq[4];
+    bool pending[4];
+    int ldr[4];
+    uint32_t off[4], cnt[4];
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-      const int32_t t = q < ntiles ? tile_q(q) : -1;
-      bool pending = t >= 0;
-      if (gather) {
-        for (int round = 0; round < 8; round++) {
-          const uint64_t act = __ballot(pending);
-          if (act == 0ull) break;
-          const int leader = __ffsll((unsigned long long)act) - 1;
-          const int32_t lt = __shfl(t, leader);
-          const bool same = pending && t == lt;
-          const uint64_t m = __ballot(same);
-          uint32_t base = 0u;
-          if (lane == leader) base = atomicAdd(&ws.tile_count[lt], (uint32_t)__popcll(m));
-          base = __shfl(base, leader);
-          if (same) {
-            rk[q] = base + (uint32_t)__popcll(m & below);
-            pending = false;
-          }
-        }
-      }
-      if (pending) rk[q] = atomicAdd(&ws.tile_count[t], 1u);
+      tq[q] = q < ntiles ? tile_q(q) : -1;
+      pending[q] = tq[q] >= 0;
+      ldr[q] = lane;
+      off[q] = 0u;
+      cnt[q] = 0u;
     }
+    for (int round = 0; gather && round < 8; round++) {
+      bool any = false;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const uint64_t act = __ballot(pending[q]);
+        if (act == 0ull) continue;
+        any = true;
+        const int L = __ffsll((unsigned long long)act) - 1;
+        const int32_t lt = __shfl(tq[q], L);
+        const bool same = pending[q] && tq[q] == lt;
+        const uint64_t m = __ballot(same);
+        if (same) {
+          ldr[q] = L;
+          off[q] = (uint32_t)__popcll(m & below);
+          pending[q] = false;
+        }
+        if (lane == L) cnt[q] = (uint32_t)__popcll(m);
+      }
+      if (!any) break;
+    }
+    uint32_t base[4], rk[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      if (pending[q]) cnt[q] = 1u;  // a group of one (ldr = lane, off = 0)
+      base[q] = cnt[q] ? atomicAdd(&ws.tile_count[tq[q]], cnt[q]) : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) rk[q] = __shfl(base[q], ldr[q]) + off[q];
     for (int q = 4; q < ntiles; q++) atomicAdd(&ws.tile_fill[tile_q(q)], 1u);
     if (vis) {
       // the record's slot in one 64-byte write: cleared gradient, ranks, rectangle, depth
