@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--tile", default=None, help="fixed tile shape WxH (with --no-autotune)")
     ap.add_argument("--lds-batch", type=int, default=256, help="with --no-autotune")
     ap.add_argument("--grid-per-cu", type=int, default=8, help="with --no-autotune")
-    ap.add_argument("--bwd-reduce", type=int, default=3, help="with --no-autotune")
+    ap.add_argument("--bwd-reduce", type=int, default=4, help="with --no-autotune")
     ap.add_argument("--order", choices=["morton", "random"], default="morton",
                     help="storage order of the Gaussians: Morton order of their means (the layout the framework "
                          "keeps), or the generator's random order")

@@ -96,7 +96,8 @@ typedef struct gsr_options {
                              (wavefront, record, component); 1 = per-lane LDS float atomics into a
                              per-batch accumulator + one device atomic per (tile, record,
                              component); 2 = as 1 after DPP sums over lane quads; 3 = as 1 after
-                             DPP sums over 16-lane rows, one LDS atomic instruction per entry */
+                             DPP sums over 16-lane rows, one LDS atomic instruction per entry;
+                             4 = as 3 with a reduce-scatter over the rows */
   float near_plane, far_plane;
   float eps2d;           /* low-pass dilation of the 2D covariance */
   float sigma_extent;    /* footprint radius in standard deviations */
@@ -168,7 +169,7 @@ typedef struct gsr_layout {
 typedef struct gsr_plan gsr_plan;
 
 /* Fills *opt with the defaults above (plain mode, 16x16 tiles, recompute backward,
- * LDS batch 128, 4 persistent workgroups per compute unit). */
+ * LDS batch 128, 4 persistent workgroups per compute unit, reverse reduction 4). */
 void gsr_default_options(gsr_options *opt);
 
 /* Creates a plan for a static problem shape.  Host only (no device call).

@@ -114,7 +114,7 @@ gsr_status validate_options(const gsr_options &o) {
   if (o.bwd_variant < GSR_BWD_AUTO || o.bwd_variant > GSR_BWD_STORED) return GSR_ERR_INVALID_ARG;
   if (o.lds_batch != 64 && o.lds_batch != 128 && o.lds_batch != 256) return GSR_ERR_INVALID_ARG;
   if (o.grid_per_cu < 1 || o.grid_per_cu > 32) return GSR_ERR_INVALID_ARG;
-  if (o.bwd_reduce < 0 || o.bwd_reduce > 3) return GSR_ERR_INVALID_ARG;
+  if (o.bwd_reduce < 0 || o.bwd_reduce > 4) return GSR_ERR_INVALID_ARG;
   if (!(o.near_plane > 0.0f) || !(o.far_plane > o.near_plane)) return GSR_ERR_INVALID_ARG;
   if (!(o.eps2d >= 0.0f) || !(o.sigma_extent > 0.0f) || !(o.jac_clamp > 0.0f)) return GSR_ERR_INVALID_ARG;
   if (!(o.alpha_min > 0.0f) || !(o.alpha_max > o.alpha_min) || !(o.alpha_max < 1.0f)) return GSR_ERR_INVALID_ARG;
@@ -441,6 +441,7 @@ void gsr_default_options(gsr_options *o) {
   o->bwd_variant = GSR_BWD_RECOMPUTE;
   o->lds_batch = 128;
   o->grid_per_cu = 4;
+  o->bwd_reduce = 4;
   o->accumulate_grads = 0;
   o->check_finite = 0;
   o->near_plane = 0.01f;
@@ -784,7 +785,7 @@ gsr_status gsr_autotune(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera
     for (int b : batches)
       for (int gpc : grids)
         for (int var : variants)
-          for (int red : {0, 2, 3}) {  // 1 (per-lane LDS atomics) is dominated by 2
+          for (int red : {0, 2, 3, 4}) {  // 1 (per-lane LDS atomics) is dominated by 2
             gsr_options o = start;
             o.tile_w = sh[0];
             o.tile_h = sh[1];

@@ -201,6 +201,8 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
 //   RED = 1: contributing lanes add their partials into an LDS accumulator
 //            of the batch (ds_add_f32, combining the four wavefronts); one
 //            device atomic per non-zero (entry, component) after the batch.
+//   RED = 2, 3, 4: as 1 after DPP sums over lane quads (2), over 16-lane
+//            rows (3), or a reduce-scatter over 16-lane rows (4).
 // Batches are aligned like the forward's (c.start + k B), so when the
 // forward's last batch `res` is the first one needed here it is used as it
 // sits in LDS, culled lists included.
@@ -211,6 +213,11 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
                                               const float *hist, Resident res) {
   const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
   const int wave = threadIdx.x >> 6, lane = lane_id();
+  // the reduce-scatter's lane roles (RED = 4): which component lane q of a
+  // 16-lane row ends with, -1 for none
+  const bool lb0 = lane & 1, lb1 = lane & 2, lb2 = lane & 4, lb3 = lane & 8;
+  const int rq = lane & 15;
+  const int comp_of_lane = rq < 8 ? (lb2 ? 5 : 0) + (lb1 ? (lb0 ? 3 : 1) : (lb0 ? 2 : 0)) : (rq == 8 ? 4 : -1);
   float S[3] = {T * o.bg[0], T * o.bg[1], T * o.bg[2]};
   const bool active = c.inside && (g[0] != 0.0f || g[1] != 0.0f || g[2] != 0.0f);
   __syncthreads();
@@ -310,6 +317,37 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
 #pragma unroll
         for (int k = 1; k < 9; k++) mine = q == k ? v[k] : mine;
         if (q < 9 && mine != 0.0f) atomicAdd(&s_acc[jj][q], mine);
+      } else if (RED == 4) {
+        // reduce-scatter over each 16-lane row: four butterfly steps between
+        // lanes i and i ^ 7, i ^ 1, i ^ 2, i ^ 8 (row_half_mirror, two quad
+        // permutations, row_ror:8), each step leaving a lane half of the
+        // components it carried, summed with its partner's; lanes 0..8 of a
+        // row end with the row sums of components 0, 2, 1, 3, 5, 7, 6, 8, 4
+        // (comp_of_lane), one LDS atomic instruction per entry
+        float r[5], t0, t1, u;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          const float keep = lb2 ? v[k + 5] : v[k], send = lb2 ? v[k] : v[k + 5];
+          r[k] = keep + dpp_or_zero<0x141>(send);  // row_half_mirror: lane i ^ 7
+        }
+        r[4] = v[4] + dpp_or_zero<0x141>(v[4]);
+        float s3[3];
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+          const float keep = lb0 ? r[k + 2] : r[k], send = lb0 ? r[k] : r[k + 2];
+          s3[k] = keep + dpp_or_zero<0xB1>(send);  // quad_perm [1,0,3,2]: lane i ^ 1
+        }
+        s3[2] = r[4] + dpp_or_zero<0xB1>(r[4]);
+        {
+          const float keep = lb1 ? s3[1] : s3[0], send = lb1 ? s3[0] : s3[1];
+          t0 = keep + dpp_or_zero<0x4E>(send);  // quad_perm [2,3,0,1]: lane i ^ 2
+          t1 = s3[2] + dpp_or_zero<0x4E>(s3[2]);
+        }
+        {
+          const float keep = lb3 ? t1 : t0, send = lb3 ? t0 : t1;
+          u = keep + dpp_or_zero<0x128>(send);  // row_ror:8: lane i ^ 8
+        }
+        if (comp_of_lane >= 0 && u != 0.0f) atomicAdd(&s_acc[jj][comp_of_lane], u);
       } else {
         // quad sums (two DPP steps), then one LDS atomic per quad and component
 #pragma unroll
@@ -553,10 +591,11 @@ int launch_tile_order(const KWs &ws, void *stream) {
   }
 
 // reverse-pass kernels also select the reduction mode; the stored-history
-// variant always takes the row-sum reduction (3)
+// variant always takes the row reduce-scatter (4)
 #define GSR_RED_CALL(KER, TW_, TH_, B_, ...)                                                           \
   do {                                                                                               \
-    if (hist) hipLaunchKernelGGL((KER<TW_, TH_, B_, 3, true>), grid, block, 0, s, __VA_ARGS__);      \
+    if (hist) hipLaunchKernelGGL((KER<TW_, TH_, B_, 4, true>), grid, block, 0, s, __VA_ARGS__);      \
+    else if (red == 4) hipLaunchKernelGGL((KER<TW_, TH_, B_, 4, false>), grid, block, 0, s, __VA_ARGS__); \
     else if (red == 3) hipLaunchKernelGGL((KER<TW_, TH_, B_, 3, false>), grid, block, 0, s, __VA_ARGS__); \
     else if (red == 2) hipLaunchKernelGGL((KER<TW_, TH_, B_, 2, false>), grid, block, 0, s, __VA_ARGS__); \
     else if (red == 1) hipLaunchKernelGGL((KER<TW_, TH_, B_, 1, false>), grid, block, 0, s, __VA_ARGS__); \

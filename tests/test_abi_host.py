@@ -69,6 +69,7 @@ def test_defaults():
     lambda p, o: setattr(o, "lds_batch", 100),
     lambda p, o: setattr(o, "grid_per_cu", 0),
     lambda p, o: setattr(o, "mode", 7),
+    lambda p, o: setattr(o, "bwd_reduce", 5),
     lambda p, o: setattr(o, "alpha_max", 1.0),
     lambda p, o: setattr(o, "T_min", 0.0),
     lambda p, o: setattr(o, "near_plane", -1.0),

@@ -152,7 +152,7 @@ def test_records_and_binning_bit_exact(scene_name, c0, ragged):
     assert np.array_equal(starts[:-1][nonempty], ob["ranges"][nonempty, 0])
 
 
-@pytest.mark.parametrize("red", [0, 1, 2, 3])
+@pytest.mark.parametrize("red", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("mode", ["plain", "batched"])
 @pytest.mark.parametrize("tile", [(16, 16), (32, 8), (8, 32)])
 def test_ragged_multiview_matches_oracle(ragged, mode, tile, red):
