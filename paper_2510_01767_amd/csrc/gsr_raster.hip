@@ -218,7 +218,9 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
   const bool lb0 = lane & 1, lb1 = lane & 2, lb2 = lane & 4, lb3 = lane & 8;
   const int rq = lane & 15;
   const int comp_of_lane = rq < 8 ? (lb2 ? 5 : 0) + (lb1 ? (lb0 ? 3 : 1) : (lb0 ? 2 : 0)) : (rq == 8 ? 4 : -1);
-  float S[3] = {T * o.bg[0], T * o.bg[1], T * o.bg[2]};
+  // gS = sum_ch g_ch S_ch with S the colour composited behind the current
+  // entry (T_final bg to start); dL/dalpha_i = T_i (g . c_i) - gS / (1 - alpha_i)
+  float gS = T * (g[0] * o.bg[0] + g[1] * o.bg[1] + g[2] * o.bg[2]);
   const bool active = c.inside && (g[0] != 0.0f || g[1] != 0.0f || g[2] != 0.0f);
   __syncthreads();
   if (threadIdx.x == 0) *s_max = 0;
@@ -249,12 +251,13 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
     }
     // entries at or past `top` contribute to no pixel
     while (cnt > 0 && (int)s_list[wave][cnt - 1] >= nb_top) cnt--;
+    const int jj_last = active ? last - (int)(lo - c.start) : 0;  // this pixel's entries: jj < jj_last
     for (int k = cnt - 1; k >= 0; k--) {
       const int jj = s_list[wave][k];
       const int64_t j = lo + jj;
       const LdsRec &R = s_rec[jj];
       const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, o.alpha_max);
-      const bool contrib = active && (int)(j - c.start) < last && a.alpha >= o.alpha_min;
+      const bool contrib = jj < jj_last && a.alpha >= o.alpha_min;
       if (__ballot(contrib) == 0ull) continue;
       // Every lane evaluates the partials (all finite: alpha <= 0.99); the
       // non-contributing ones get zero weights, so they add exact zeros.
@@ -265,13 +268,11 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
       const float wgt = contrib ? a.alpha * Ti : 0.0f;
       const float col[3] = {R.r2.x, R.r2.y, R.r2.z};
       float v[9];
-      float dLda = 0.0f;
+      const float gc = __fmaf_rn(g[2], col[2], __fmaf_rn(g[1], col[1], g[0] * col[0]));
+      const float dLda = __fmaf_rn(Ti, gc, -gS * inv_om);
+      gS = __fmaf_rn(wgt, gc, gS);
 #pragma unroll
-      for (int ch = 0; ch < 3; ch++) {
-        dLda += g[ch] * (Ti * col[ch] - S[ch] * inv_om);
-        v[6 + ch] = g[ch] * wgt;
-        S[ch] = __fmaf_rn(wgt, col[ch], S[ch]);
-      }
+      for (int ch = 0; ch < 3; ch++) v[6 + ch] = g[ch] * wgt;
       // the geometric partials vanish where alpha is clamped at alpha_max
       const float dLdam = (contrib && a.raw < o.alpha_max) ? dLda : 0.0f;
       const float gp = dLdam * a.alpha;  // dL/dp
