@@ -311,24 +311,26 @@ __device__ __forceinline__ void sh_grad(T x, T y, T z, const T *w, T g[3]) {
 // identical float32 expression and replay the same skip / stop decisions.
 struct PairAlpha {
   float dx, dy, G, raw, alpha;
+  float t, cdy;  // a dx + b dy and c dy, reused by the reverse partials
 };
 
-// pmin is a per-record lower bound on the exponent below which o e^p cannot
+// The record holds the exponent's coefficients in base 2, so the exponent
+// p log2 e = a dx^2 + b dx dy + c dy^2 = (a dx + b dy) dx + (c dy) dy takes
+// five operations and feeds the hardware 2^x directly (for pmin <= p <= 0,
+// |p log2 e| < 12: the instruction's error stays below 6e-7 relative).
+// pmin2 = pmin log2 e is a per-record lower bound below which o e^p cannot
 // reach alpha_min (ln(alpha_min / o) minus a slack): such pairs skip the
 // exponential; the alpha test itself still decides every pair.
 __device__ __forceinline__ PairAlpha pair_alpha(float pxc, float pyc, const float4 &r0, const float4 &r1,
-                                                float pmin, float alpha_max) {
+                                                float pmin2, float alpha_max) {
   PairAlpha a;
   a.dx = (pxc - r0.x) - r0.z;
   a.dy = (pyc - r0.y) - r0.w;
-  // p = -(A dx^2 + C dy^2) / 2 - B dx dy
-  const float quad = __fmaf_rn(r1.x * a.dx, a.dx, r1.z * a.dy * a.dy);
-  const float p = __fmaf_rn(-0.5f, quad, -(r1.y * a.dx * a.dy));
-  // e^p as 2^(p log2 e) on the hardware exponential: for pmin <= p <= 0
-  // (|p log2 e| < 12) the rounding of the product and the instruction's own
-  // error stay below 6e-7 relative
-  const float e = __builtin_amdgcn_exp2f(p * 1.44269504088896341f);
-  a.G = (p > 0.0f || p < pmin) ? -1.0f : e;  // G < 0 marks a skipped pair
+  a.t = __fmaf_rn(r1.x, a.dx, r1.y * a.dy);
+  a.cdy = r1.z * a.dy;
+  const float p2 = __fmaf_rn(a.t, a.dx, a.cdy * a.dy);
+  const float e = __builtin_amdgcn_exp2f(p2);
+  a.G = (p2 > 0.0f || p2 < pmin2) ? -1.0f : e;  // G < 0 marks a skipped pair
   a.raw = r1.w * a.G;
   a.alpha = fminf(alpha_max, a.raw);
   return a;
@@ -358,6 +360,7 @@ __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 // ------------------------------------------------------------ shared helpers
 
 constexpr int kBlock = 256;
+constexpr double kLog2e = 1.44269504088896340736;  // log2(e)
 
 __device__ __forceinline__ const float4 *rec_ptr(const KWs &ws, int64_t r) {
   return reinterpret_cast<const float4 *>(ws.records) + r * kRecordFloat4;

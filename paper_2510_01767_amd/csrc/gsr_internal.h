@@ -65,8 +65,11 @@ struct KGrads {
 
 // Record of one (view, Gaussian) pair, 64 bytes (4 x float4):
 //   r0 = mean2d as float pairs (hi x, hi y, lo x, lo y): mean = hi + lo
-//   r1 = conic (A, B, C), opacity
-//   r2 = colour (r, g, b), pmin (exponent below which alpha < alpha_min)
+//   r1 = the exponent's coefficients in base 2, (a, b, c) = log2(e) (-A/2,
+//        -B, -C/2) for the conic (A, B, C), so that the exponent is
+//        p log2(e) = a dx^2 + b dx dy + c dy^2; opacity
+//   r2 = colour (r, g, b), pmin log2(e) (pmin: exponent below which
+//        alpha < alpha_min)
 //   r3 = rect (x0 | y0 << 16, x1 | y1 << 16), depth (camera z, float bits),
 //        reach of the alpha >= alpha_min ellipse in pixels (float bits)
 constexpr int kRecordFloat4 = 4;

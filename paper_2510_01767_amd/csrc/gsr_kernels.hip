@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera 
   // (the float32 exponent and opacity are accurate to ~1e-6).  Below pmin the
   // float32 exponent cannot give alpha >= alpha_min (same slack).
   const double c2 = keep ? 2.0 * log(g.opac / (double)o.alpha_min) + 1e-5 : 0.0;
-  const float pmin = c2 > 0.0 ? (float)(-0.5 * c2) : 0.0f;
+  const float pmin = c2 > 0.0 ? (float)(-0.5 * c2 * kLog2e) : 0.0f;  // in base 2, like the record's exponent
   uint32_t bits = (valid && or_bits) ? ws.view_bits[i] : 0u;
   uint32_t fresh = 0u;  // views found visible by this call
   const int lane = lane_id();
@@ -113,7 +113,8 @@ __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera 
       float4 *rec = reinterpret_cast<float4 *>(ws.records) + r * kRecordFloat4;
       const float mxh = (float)P.mx, myh = (float)P.my;
       rec[0] = make_float4(mxh, myh, (float)(P.mx - (double)mxh), (float)(P.my - (double)myh));
-      rec[1] = make_float4((float)P.A, (float)P.B, (float)P.C, (float)g.opac);
+      rec[1] = make_float4((float)(-0.5 * kLog2e * P.A), (float)(-kLog2e * P.B), (float)(-0.5 * kLog2e * P.C),
+                           (float)g.opac);
       // the reach gets a relative and an absolute pad, so no pixel that the
       // float32 alpha test accepts lies outside it; -1 when even the centre
       // cannot reach alpha_min

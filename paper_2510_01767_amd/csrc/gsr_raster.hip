@@ -61,20 +61,20 @@ __device__ __forceinline__ void tile_ctx(const KWs &ws, const ViewInfo *views, i
 }
 
 struct LdsRec {
-  float4 r0, r1, r2;  // mean (hi, lo), conic + opacity, colour + pmin
+  float4 r0, r1, r2;  // mean (hi, lo), base-2 exponent coefficients + opacity, colour + base-2 pmin
   float reach;
 };
 
 // Can the entry's alpha reach alpha_min at some pixel centre of this lane's
 // wavefront strip?  Two tests against the box of the strip's pixel centres:
 // the circle of radius `reach`, then the ellipse itself.  alpha >= alpha_min
-// needs q(d) = A dx^2 + 2 B dx dy + C dy^2 <= c2 = 2 ln(o / alpha_min)
-// (= -2 pmin, slack included).  q is convex with its minimum 0 at the mean,
-// so over a box that does not hold the mean its minimum lies on an edge that
-// faces the mean, where q is a 1D quadratic minimised in closed form.  The
-// box offsets are formed like the per-pixel offsets ((centre - hi) - lo), so
-// they differ from what a pixel evaluates only by relative roundings of a
-// few 1e-7; the threshold carries 1e-4 relative and absolute on top.
+// needs the base-2 exponent q(d) = a dx^2 + b dx dy + c dy^2 >= pmin2
+// (slack included).  q is concave with its maximum 0 at the mean, so over a
+// box that does not hold the mean its maximum lies on an edge that faces the
+// mean, where q is a 1D quadratic maximised in closed form.  The box offsets
+// are formed like the per-pixel offsets ((centre - hi) - lo), so they differ
+// from what a pixel evaluates only by relative roundings of a few 1e-7; the
+// threshold carries 1e-4 relative and 1e-4 log2(e) / 2 absolute on top.
 __device__ __forceinline__ bool reaches_strip(const LdsRec &R, const TileCtx &c) {
   const float reach = R.reach;
   if (reach < 0.0f) return false;
@@ -86,19 +86,19 @@ __device__ __forceinline__ bool reaches_strip(const LdsRec &R, const TileCtx &c)
   const float y0 = (c.wy0 - R.r0.y) - R.r0.w, y1 = (c.wy1 - R.r0.y) - R.r0.w;
   const bool out_x = x0 > 0.0f || x1 < 0.0f, out_y = y0 > 0.0f || y1 < 0.0f;
   if (!out_x && !out_y) return true;
-  const float A = R.r1.x, Bc = R.r1.y, Cc = R.r1.z;
-  float qmin = 3.0e38f;
+  const float a = R.r1.x, b = R.r1.y, cc = R.r1.z;
+  float qmax = -3.0e38f;
   if (out_x) {
     const float X = x0 > 0.0f ? x0 : x1;
-    const float Y = fminf(fmaxf(-Bc * X / Cc, y0), y1);
-    qmin = fminf(qmin, A * X * X + 2.0f * Bc * X * Y + Cc * Y * Y);
+    const float Y = fminf(fmaxf(-b * X / (2.0f * cc), y0), y1);
+    qmax = fmaxf(qmax, a * X * X + b * X * Y + cc * Y * Y);
   }
   if (out_y) {
     const float Y = y0 > 0.0f ? y0 : y1;
-    const float X = fminf(fmaxf(-Bc * Y / A, x0), x1);
-    qmin = fminf(qmin, A * X * X + 2.0f * Bc * X * Y + Cc * Y * Y);
+    const float X = fminf(fmaxf(-b * Y / (2.0f * a), x0), x1);
+    qmax = fmaxf(qmax, a * X * X + b * X * Y + cc * Y * Y);
   }
-  return qmin <= -2.0f * R.r2.w * 1.0001f + 1e-4f;
+  return qmax >= R.r2.w * 1.0001f - 7.2135e-5f;
 }
 
 __device__ __forceinline__ void load_batch(const KWs &ws, int64_t lo, int nb, LdsRec *s_rec, uint32_t *s_idx,
@@ -277,8 +277,10 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
       const float dLdam = (contrib && a.raw < o.alpha_max) ? dLda : 0.0f;
       const float gp = dLdam * a.alpha;  // dL/dp
       v[5] = dLdam * a.G;
-      v[0] = gp * __fmaf_rn(R.r1.x, a.dx, R.r1.y * a.dy);
-      v[1] = gp * __fmaf_rn(R.r1.y, a.dx, R.r1.z * a.dy);
+      // dp/dmean = (A dx + B dy, B dx + C dy) = -(2 a dx + b dy, b dx + 2 c dy) ln 2
+      const float gq = gp * -0.693147180559945309f;
+      v[0] = gq * __fmaf_rn(R.r1.x, a.dx, a.t);
+      v[1] = gq * __fmaf_rn(R.r1.y, a.dx, a.cdy + a.cdy);
       v[2] = -0.5f * gp * a.dx * a.dx;
       v[3] = -gp * a.dx * a.dy;
       v[4] = -0.5f * gp * a.dy * a.dy;

@@ -104,7 +104,10 @@ def test_records_and_binning_bit_exact(scene_name, c0, ragged):
         rv = rec[v * n:(v + 1) * n][sel]
         m2 = rv[:, 0:2].astype(np.float64) + rv[:, 2:4].astype(np.float64)
         np.testing.assert_allclose(m2, o["mean2d"][:, sel].T, rtol=0, atol=1e-9 * max(1.0, np.abs(o["mean2d"]).max()))
-        np.testing.assert_allclose(rv[:, 4:7], o["conic"][:, sel].T, rtol=3e-7)
+        # the exponent's base-2 coefficients log2(e) (-A/2, -B, -C/2), rounded once
+        L2E = 1.0 / np.log(2.0)
+        coef = np.stack([-0.5 * L2E * o["conic"][0], -L2E * o["conic"][1], -0.5 * L2E * o["conic"][2]])
+        np.testing.assert_allclose(rv[:, 4:7], coef[:, sel].T, rtol=3e-7)
         np.testing.assert_allclose(rv[:, 7], o["opacity"][sel], rtol=3e-7)
         # colours are evaluated in float32 (48 SH terms): ~1e-7 absolute error
         np.testing.assert_allclose(rv[:, 8:11], o["color"][:, sel].T, rtol=0, atol=2e-6)
@@ -113,7 +116,7 @@ def test_records_and_binning_bit_exact(scene_name, c0, ragged):
         # alpha clears alpha_min (used to cull entries per wavefront)
         reach = rv[:, 15].astype(np.float64)
         # pmin lower-bounds the exponent of every pair the alpha test accepts
-        pmin = rv[:, 11].astype(np.float64)
+        pmin = rv[:, 11].astype(np.float64) * np.log(2.0)  # stored in base 2
         np.testing.assert_array_less(pmin, np.log(parity.opts_for().alpha_min / o["opacity"][sel]) + 1e-12)
         idx = np.nonzero(sel)[0]
         W, H = scene.cameras[v]["W"], scene.cameras[v]["H"]
