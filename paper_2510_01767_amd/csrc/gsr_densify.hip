@@ -152,19 +152,13 @@ __device__ __forceinline__ void copy_plane(const KDensify &k, const int *dec, co
 #pragma unroll
   for (int r = 0; r < kItems; r++) {
     const int c = dec[r] & 3, kind = dec[r] >> 2;
-    if (c == 0) continue;
-    if (MODE == kMoments) {
-      dst[pos[r]] = v[r];
-      if (c == 2) dst[pos[r] + 1] = 0.0f;  // a clone or a child starts from zero moments
-    } else if (MODE == kMeans) {
-      if (kind == 2) continue;  // the children's means are written apart
-      dst[pos[r]] = v[r];
-      if (c == 2) dst[pos[r] + 1] = v[r];
-    } else {
-      const float x = (MODE == kLogScales && kind == 2) ? v[r] - k.child_dlog : v[r];
-      dst[pos[r]] = x;
-      if (c == 2) dst[pos[r] + 1] = x;
-    }
+    // the children's means are written apart; a moment of a clone or a
+    // child starts from zero
+    const bool skip = MODE == kMeans && kind == 2;
+    const float x = (MODE == kLogScales && kind == 2) ? v[r] - k.child_dlog : v[r];
+    const float x1 = MODE == kMoments ? 0.0f : x;
+    if (c != 0 && !skip) dst[pos[r]] = x;
+    if (c == 2 && !skip) dst[pos[r] + 1] = x1;
   }
 }
 
@@ -220,30 +214,28 @@ __global__ __launch_bounds__(kBlock) void k_densify_apply(KDensify k) {
       }
     }
   }
-  // the planes, spread over gridDim.y workgroups per chunk: 11 + SH planes of
-  // parameters, then the same planes of each moment when present
-  const int P = 11 + k.sh_planes;
-  const int Q = k.om[0] ? 3 * P : P;
-  for (int q = blockIdx.y; q < Q; q += gridDim.y) {
-    const int which = q / P, r = q % P;  // 0 parameters, 1 first moments, 2 second moments
-    if (which > 0) {
-      const int g = r < 3 ? 0 : r < 6 ? 1 : r < 10 ? 2 : r < 11 ? 3 : 4;
-      const int p = r - (g == 0 ? 0 : g == 1 ? 3 : g == 2 ? 6 : g == 3 ? 10 : 11);
-      const float *src = (which == 1 ? k.m[g] : k.v[g]) + p * n + first;
-      float *dst = (which == 1 ? k.om[g] : k.ov[g]) + p * no;
-      copy_plane<kMoments>(k, mdec, mpos, src, dst);
-    } else if (r < 3) {
-      copy_plane<kMeans>(k, mdec, mpos, k.mean + r * n + first, k.o_mean + r * no);
-    } else if (r < 6) {
-      copy_plane<kLogScales>(k, mdec, mpos, k.ls + (r - 3) * n + first, k.o_ls + (r - 3) * no);
-    } else if (r < 10) {
-      copy_plane<kCopied>(k, mdec, mpos, k.quat + (r - 6) * n + first, k.o_quat + (r - 6) * no);
-    } else if (r < 11) {
-      copy_plane<kCopied>(k, mdec, mpos, k.opa + first, k.o_opa);
-    } else {
-      copy_plane<kCopied>(k, mdec, mpos, k.sh + (r - 11) * n + first, k.o_sh + (r - 11) * no);
+  // the planes, spread over the chunk's kPlaneSplit workgroups (plane number
+  // u of the parameters, then of each moment when present, goes to the
+  // workgroup u mod kPlaneSplit)
+  int u = 0;
+  const int y = blockIdx.y;
+  constexpr int G = kPlaneSplit;  // gridDim.y
+  for (int p = 0; p < 3; p++, u++)
+    if (u % G == y) copy_plane<kMeans>(k, mdec, mpos, k.mean + p * n + first, k.o_mean + p * no);
+  for (int p = 0; p < 3; p++, u++)
+    if (u % G == y) copy_plane<kLogScales>(k, mdec, mpos, k.ls + p * n + first, k.o_ls + p * no);
+  for (int p = 0; p < 4; p++, u++)
+    if (u % G == y) copy_plane<kCopied>(k, mdec, mpos, k.quat + p * n + first, k.o_quat + p * no);
+  if (u++ % G == y) copy_plane<kCopied>(k, mdec, mpos, k.opa + first, k.o_opa);
+  for (int p = 0; p < k.sh_planes; p++, u++)
+    if (u % G == y) copy_plane<kCopied>(k, mdec, mpos, k.sh + p * n + first, k.o_sh + p * no);
+  if (!k.om[0]) return;
+  const int rows[5] = {3, 3, 4, 1, k.sh_planes};
+  for (int g = 0; g < 5; g++)
+    for (int p = 0; p < rows[g]; p++) {
+      if (u++ % G == y) copy_plane<kMoments>(k, mdec, mpos, k.m[g] + p * n + first, k.om[g] + p * no);
+      if (u++ % G == y) copy_plane<kMoments>(k, mdec, mpos, k.v[g] + p * n + first, k.ov[g] + p * no);
     }
-  }
 }
 
 }  // namespace
