@@ -399,43 +399,39 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(KWs ws, int64_t lo,
 
 // --------------------------------------------------------------------- emit
 
+// One thread per (view, Gaussian) pair: grid x over Gaussians, y over the
+// views (or the one view of a plain-mode call), so the pairs of one Gaussian
+// are placed in parallel rather than one after another.
 __global__ __launch_bounds__(kBlock) void k_emit(KWs ws, int64_t n, int n_views, int view_only) {
-  __shared__ ViewInfo s_view[GSR_MAX_VIEWS];
-  for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_view[v] = ws.views[v];
-  __syncthreads();
+  const int v = view_only >= 0 ? view_only : (int)blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint32_t bits = ws.view_bits[i];
-  if (view_only >= 0) bits &= 1u << view_only;
-  for (; bits; bits &= bits - 1) {
-    const int v = __ffs(bits) - 1;
-    const int64_t r = (int64_t)v * n + i;
-    const uint4 *sl = reinterpret_cast<const uint4 *>(ws.grad2d + r * kGrad2dStride);
-    const uint4 s2 = sl[2], s3 = sl[3];
-    const ViewInfo &vi = s_view[v];
-    const int x0 = s3.y & 0xffff, y0 = s3.y >> 16, x1 = s3.z & 0xffff;
-    const int wx = x1 - x0 + 1, ntiles = wx * ((int)(s3.z >> 16) - y0 + 1);
-    const uint64_t key = ((uint64_t)s3.w << 32) | (uint64_t)(uint32_t)r;
-    const uint32_t rk[4] = {s2.y, s2.z, s2.w, s3.x};
-    // the ranked first four tiles (row-major), their loads issued together
+  if (i >= n || !((ws.view_bits[i] >> v) & 1u)) return;
+  const ViewInfo vi = ws.views[v];
+  const int64_t r = (int64_t)v * n + i;
+  const uint4 *sl = reinterpret_cast<const uint4 *>(ws.grad2d + r * kGrad2dStride);
+  const uint4 s2 = sl[2], s3 = sl[3];
+  const int x0 = s3.y & 0xffff, y0 = s3.y >> 16, x1 = s3.z & 0xffff;
+  const int wx = x1 - x0 + 1, ntiles = wx * ((int)(s3.z >> 16) - y0 + 1);
+  const uint64_t key = ((uint64_t)s3.w << 32) | (uint64_t)(uint32_t)r;
+  const uint32_t rk[4] = {s2.y, s2.z, s2.w, s3.x};
+  // the ranked first four tiles (row-major), their loads issued together
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      if (q < ntiles) {
-        const int dy = q / wx, dx = q - dy * wx;
-        const int64_t t = vi.tile_base + (int64_t)(y0 + dy) * vi.tiles_x + (x0 + dx);
-        const uint64_t slot = (uint64_t)ws.tile_start[t] + rk[q];
-        if (slot < (uint64_t)ws.capacity && slot < (uint64_t)ws.tile_start[t + 1]) ws.keys[slot] = key;
-      }
-    }
-    // the overflow entries of large footprints follow the ranked ones
-    // (tile_fill counted them; counting it back down places them)
-    for (int q = 4; q < ntiles; q++) {
+  for (int q = 0; q < 4; q++) {
+    if (q < ntiles) {
       const int dy = q / wx, dx = q - dy * wx;
       const int64_t t = vi.tile_base + (int64_t)(y0 + dy) * vi.tiles_x + (x0 + dx);
-      const uint32_t rank = ws.tile_count[t] + atomicSub(&ws.tile_fill[t], 1u) - 1u;
-      const uint64_t slot = (uint64_t)ws.tile_start[t] + rank;
+      const uint64_t slot = (uint64_t)ws.tile_start[t] + rk[q];
       if (slot < (uint64_t)ws.capacity && slot < (uint64_t)ws.tile_start[t + 1]) ws.keys[slot] = key;
     }
+  }
+  // the overflow entries of large footprints follow the ranked ones
+  // (tile_fill counted them; counting it back down places them)
+  for (int q = 4; q < ntiles; q++) {
+    const int dy = q / wx, dx = q - dy * wx;
+    const int64_t t = vi.tile_base + (int64_t)(y0 + dy) * vi.tiles_x + (x0 + dx);
+    const uint32_t rank = ws.tile_count[t] + atomicSub(&ws.tile_fill[t], 1u) - 1u;
+    const uint64_t slot = (uint64_t)ws.tile_start[t] + rank;
+    if (slot < (uint64_t)ws.capacity && slot < (uint64_t)ws.tile_start[t + 1]) ws.keys[slot] = key;
   }
 }
 
@@ -1000,7 +996,8 @@ int launch_scan(const KWs &ws, int64_t lo, int64_t hi, int64_t base, int view_lo
 }
 
 int launch_emit(const KWs &ws, int64_t n, int n_views, int view_only, void *stream) {
-  hipLaunchKernelGGL(k_emit, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, ws, n, n_views, view_only);
+  const unsigned gy = view_only >= 0 ? 1u : (unsigned)n_views;
+  hipLaunchKernelGGL(k_emit, dim3(grid_for(n), gy), dim3(kBlock), 0, (hipStream_t)stream, ws, n, n_views, view_only);
   return last_err();
 }
 
