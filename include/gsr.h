@@ -401,8 +401,8 @@ gsr_status gsr_densify_workspace_size(int64_t n, size_t *bytes);
 /* First half: decides every Gaussian and counts the outputs.  g (device
  * planes of n Gaussians, keep optional), stats (both pointers required) and
  * in_block (device [n] u8, required when selective = 1) are read on
- * `stream`; the stream is synchronized and *n_out (host) receives the
- * output count.  The workspace keeps the per-block offsets for
+ * `stream` (with n = 0 they may be null); the stream is synchronized and
+ * *n_out (host) receives the output count.  The workspace keeps the per-block offsets for
  * gsr_densify_apply.  GSR_ERR_INVALID_ARG for n < 0, sh_degree outside
  * 0..3, a null required pointer, clone_max_scale <= 0, min_opacity outside
  * [0, 1) or a NaN threshold; GSR_ERR_WORKSPACE_TOO_SMALL; GSR_ERR_HIP. */

@@ -268,12 +268,12 @@ namespace {
 gsr_status fill_densify(gsr::KDensify &k, int64_t n, int32_t sh_degree, const gsr_densify_opts *o,
                         const gsr_gaussians *g, const gsr_stats *stats, const uint8_t *in_block, void *ws,
                         size_t ws_bytes) {
-  if (n < 0 || sh_degree < 0 || sh_degree > 3 || !o || !g || !stats || !stats->grad2d_norm_sum ||
-      !stats->visible_count || !ws)
+  if (n < 0 || sh_degree < 0 || sh_degree > 3 || !o || !g || !stats || !ws) return GSR_ERR_INVALID_ARG;
+  // the per-Gaussian arrays may be null when there are no Gaussians
+  if (n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh ||
+                !stats->grad2d_norm_sum || !stats->visible_count))
     return GSR_ERR_INVALID_ARG;
-  if (n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh))
-    return GSR_ERR_INVALID_ARG;
-  if (o->selective && !in_block) return GSR_ERR_INVALID_ARG;
+  if (n > 0 && o->selective && !in_block) return GSR_ERR_INVALID_ARG;
   if (std::isnan(o->grad_threshold) || !(o->clone_max_scale > 0.0f) || !(o->min_opacity >= 0.0f) ||
       !(o->min_opacity < 1.0f) || std::isnan(o->max_world_scale) || std::isinf(o->clone_max_scale))
     return GSR_ERR_INVALID_ARG;
@@ -340,10 +340,11 @@ extern "C" gsr_status gsr_densify_apply(int64_t n, int32_t sh_degree, const gsr_
   gsr::KDensify k;
   const gsr_status st = fill_densify(k, n, sh_degree, opts, g, stats, in_block, ws, ws_bytes);
   if (st != GSR_OK) return st;
-  if (n_out < 0 || (n > 0 && !samples) || (n_out > 0 && !full(out))) return GSR_ERR_INVALID_ARG;
+  if (n_out < 0) return GSR_ERR_INVALID_ARG;
+  if (n_out == 0 || n == 0) return GSR_OK;  // nothing to write
+  if (!samples || !full(out)) return GSR_ERR_INVALID_ARG;
   const bool moments = m_out || v_out || m_in || v_in;
   if (moments && !(full(m_in) && full(v_in) && full(m_out) && full(v_out))) return GSR_ERR_INVALID_ARG;
-  if (n_out == 0 || n == 0) return GSR_OK;
   k.samples = samples;
   k.n_out = n_out;
   k.o_mean = out->means;

@@ -95,6 +95,10 @@ def test_densify_edge_sizes():
         inputs = make_inputs(n, 0, scenes.SEED_BASE + 650 + n)
         ora, out, mo, vo, parent = run_both(*inputs, 0.3, 0.05, 0.005, 0.0, True, True, True)
         compare(ora, out, mo, vo, parent)
+    # no Gaussians at all
+    announce("densify empty")
+    ora, out, mo, vo, parent = run_both(*make_inputs(0, 1, 8), 0.3, 0.05, 0.005, 0.0, True, True, True)
+    assert len(parent) == 0 and len(ora["parent"]) == 0
     # everything pruned: no outputs
     announce("densify all pruned")
     P, S, cnt, blk, keep, samples, m, v = make_inputs(3000, 0, 7)

@@ -72,3 +72,17 @@ def test_device_partition_at_the_bench_size():
                                 pixels=(960 * 540, 1920 * 1080))
     work = check(pi, 8, 3)
     print("workloads", work.tolist(), flush=True)
+
+
+def test_device_partition_edge_cases():
+    # one block (no split), a camera without pixels, and no centres at all
+    announce("partition edge cases")
+    pi = scenes.partition_input(seed=scenes.SEED_BASE + 420, n=3000, n_views=6, pixels=(500, 900))
+    check(pi, 1, 3)
+    off = np.concatenate([pi.offsets[:3], pi.offsets[2:]])
+    empty_cam = scenes.PartitionInput(aabb=pi.aabb, centers=pi.centers, points=pi.points, offsets=off)
+    work = check(empty_cam, 5, 3)
+    assert work.sum() > 0
+    no_centres = scenes.PartitionInput(aabb=pi.aabb, centers=np.zeros((3, 0), f32), points=pi.points,
+                                       offsets=pi.offsets)
+    check(no_centres, 4, 2)
