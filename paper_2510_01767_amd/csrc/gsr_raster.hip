@@ -34,6 +34,7 @@ struct TileCtx {
   int64_t start, end;  // entry range [start, end) in keys
   int64_t pix;         // pixel index within the view
   float wx0, wx1, wy0, wy1;  // pixel-centre box of this lane's wavefront
+  int sw, sh, snx;           // sub-block width and height, sub-blocks per strip row
 };
 
 template <int TW, int TH>
@@ -46,14 +47,22 @@ __device__ __forceinline__ void tile_ctx(const KWs &ws, const ViewInfo *views, i
   c.vi = views[c.v];
   const int64_t local = t - c.vi.tile_base;
   const int tx0 = (int)(local % c.vi.tiles_x) * TW, ty0 = (int)(local / c.vi.tiles_x) * TH;
-  c.px = tx0 + (int)(threadIdx.x % TW);
-  c.py = ty0 + (int)(threadIdx.x / TW);
+  // Each wavefront owns a strip of 64 pixels (TW x kRows) and each 16-lane
+  // row of it a sub-block of 16 pixels: 4 x 4 for 8- and 16-wide tiles, 8 x 2
+  // for 32-wide ones (SNX sub-blocks side by side).
+  constexpr int SW = TW == 32 ? 8 : 4, SH = 16 / SW, SNX = TW / SW;
+  static_assert((kRows / SH) * SNX == 4, "four sub-blocks per strip");
+  const int wave = threadIdx.x >> 6, lane = (int)threadIdx.x & 63, row = lane >> 4, sl = lane & 15;
+  c.px = tx0 + (row % SNX) * SW + sl % SW;
+  c.py = ty0 + wave * kRows + (row / SNX) * SH + sl / SW;
+  c.sw = SW;
+  c.sh = SH;
+  c.snx = SNX;
   c.inside = c.px < c.vi.W && c.py < c.vi.H;
   c.pix = (int64_t)c.py * c.vi.W + c.px;
   c.start = ws.tile_start[t];
   c.end = min((int64_t)ws.tile_start[t + 1], ws.capacity);
   if (c.end < c.start) c.end = c.start;
-  const int wave = threadIdx.x >> 6;
   c.wx0 = (float)tx0 + 0.5f;
   c.wx1 = (float)(tx0 + TW) - 0.5f;
   c.wy0 = (float)(ty0 + wave * kRows) + 0.5f;
@@ -65,6 +74,25 @@ struct LdsRec {
   float reach;
 };
 
+// A batch of records in LDS as separate arrays: the four 16-lane rows of a
+// wavefront read four different entries at once, which in a 64-byte record
+// array would start on the same banks.
+template <int B>
+struct LdsBatch {
+  float4 r0[B], r1[B], r2[B];
+  float reach[B];
+};
+
+template <int B>
+__device__ __forceinline__ LdsRec rec_at(const LdsBatch<B> &s, int j) {
+  LdsRec R;
+  R.r0 = s.r0[j];
+  R.r1 = s.r1[j];
+  R.r2 = s.r2[j];
+  R.reach = s.reach[j];
+  return R;
+}
+
 // Can the entry's alpha reach alpha_min at some pixel centre of this lane's
 // wavefront strip?  Two tests against the box of the strip's pixel centres:
 // the circle of radius `reach`, then the ellipse itself.  alpha >= alpha_min
@@ -75,15 +103,15 @@ struct LdsRec {
 // are formed like the per-pixel offsets ((centre - hi) - lo), so they differ
 // from what a pixel evaluates only by relative roundings of a few 1e-7; the
 // threshold carries 1e-4 relative and 1e-4 log2(e) / 2 absolute on top.
-__device__ __forceinline__ bool reaches_strip(const LdsRec &R, const TileCtx &c) {
+__device__ __forceinline__ bool reaches_box(const LdsRec &R, float bx0, float bx1, float by0, float by1) {
   const float reach = R.reach;
   if (reach < 0.0f) return false;
   const float mx = R.r0.x + R.r0.z, my = R.r0.y + R.r0.w;
-  const float ddx = fmaxf(0.0f, fmaxf(c.wx0 - mx, mx - c.wx1));
-  const float ddy = fmaxf(0.0f, fmaxf(c.wy0 - my, my - c.wy1));
+  const float ddx = fmaxf(0.0f, fmaxf(bx0 - mx, mx - bx1));
+  const float ddy = fmaxf(0.0f, fmaxf(by0 - my, my - by1));
   if (ddx * ddx + ddy * ddy > reach * reach) return false;
-  const float x0 = (c.wx0 - R.r0.x) - R.r0.z, x1 = (c.wx1 - R.r0.x) - R.r0.z;
-  const float y0 = (c.wy0 - R.r0.y) - R.r0.w, y1 = (c.wy1 - R.r0.y) - R.r0.w;
+  const float x0 = (bx0 - R.r0.x) - R.r0.z, x1 = (bx1 - R.r0.x) - R.r0.z;
+  const float y0 = (by0 - R.r0.y) - R.r0.w, y1 = (by1 - R.r0.y) - R.r0.w;
   const bool out_x = x0 > 0.0f || x1 < 0.0f, out_y = y0 > 0.0f || y1 < 0.0f;
   if (!out_x && !out_y) return true;
   const float a = R.r1.x, b = R.r1.y, cc = R.r1.z;
@@ -101,34 +129,47 @@ __device__ __forceinline__ bool reaches_strip(const LdsRec &R, const TileCtx &c)
   return qmax >= R.r2.w * 1.0001f - 7.2135e-5f;
 }
 
-__device__ __forceinline__ void load_batch(const KWs &ws, int64_t lo, int nb, LdsRec *s_rec, uint32_t *s_idx,
+template <int B>
+__device__ __forceinline__ void load_batch(const KWs &ws, int64_t lo, int nb, LdsBatch<B> &s_rec, uint32_t *s_idx,
                                            float *s_depth = nullptr) {
   if ((int)threadIdx.x < nb) {
     const uint32_t r = (uint32_t)ws.keys[lo + threadIdx.x];
     const float4 *rec = rec_ptr(ws, r);
-    s_rec[threadIdx.x].r0 = rec[0];
-    s_rec[threadIdx.x].r1 = rec[1];
-    s_rec[threadIdx.x].r2 = rec[2];
+    s_rec.r0[threadIdx.x] = rec[0];
+    s_rec.r1[threadIdx.x] = rec[1];
+    s_rec.r2[threadIdx.x] = rec[2];
     const uint4 r3 = reinterpret_cast<const uint4 *>(rec)[3];
-    s_rec[threadIdx.x].reach = __uint_as_float(r3.w);
+    s_rec.reach[threadIdx.x] = __uint_as_float(r3.w);
     if (s_idx) s_idx[threadIdx.x] = r;
     if (s_depth) s_depth[threadIdx.x] = __uint_as_float(r3.z);
   }
 }
 
-// The wavefront's kept entries of the batch, in list order.  Returns the count.
+// The kept entries of the batch for each of the wavefront's four
+// sub-blocks, in list order: an entry is tested against the strip, then
+// against each sub-block.  lists[q] of sub-block q gets cnt[q] entries;
+// returns the count of this lane's own sub-block.
 template <int B>
-__device__ __forceinline__ int strip_list(const LdsRec *s_rec, int nb, const TileCtx &c, uint16_t *list) {
+__device__ __forceinline__ int sub_lists(const LdsBatch<B> &s_rec, int nb, const TileCtx &c, uint8_t (*lists)[B],
+                                         int cnt[4]) {
+  static_assert(B <= 256, "byte indices");
   const int lane = lane_id();
-  int cnt = 0;
+  const uint64_t below = (1ull << lane) - 1ull;
+  cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0;
   for (int jb = 0; jb < nb; jb += 64) {
     const int j = jb + lane;
-    const bool keep = j < nb && reaches_strip(s_rec[j], c);
-    const uint64_t m = __ballot(keep);
-    if (keep) list[cnt + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)j;
-    cnt += __popcll(m);
+    const LdsRec R = rec_at(s_rec, j < nb ? j : 0);
+    const bool strip = j < nb && reaches_box(R, c.wx0, c.wx1, c.wy0, c.wy1);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const float bx0 = c.wx0 + (float)((q % c.snx) * c.sw), by0 = c.wy0 + (float)((q / c.snx) * c.sh);
+      const bool keep = strip && reaches_box(R, bx0, bx0 + (float)(c.sw - 1), by0, by0 + (float)(c.sh - 1));
+      const uint64_t m = __ballot(keep);
+      if (keep) lists[q][cnt[q] + __popcll(m & below)] = (uint8_t)j;
+      cnt[q] += __popcll(m);
+    }
   }
-  return cnt;
+  return cnt[lane >> 4];
 }
 
 // The batch that a tile pass left in LDS: entries [lo, lo + nb) of the list
@@ -136,7 +177,7 @@ __device__ __forceinline__ int strip_list(const LdsRec *s_rec, int nb, const Til
 // in s_list).  nb == 0: nothing usable.
 struct Resident {
   int64_t lo;
-  int nb, cnt;
+  int nb, cnt;  // cnt: this lane's sub-block list length
 };
 
 // Front-to-back compositing of one tile.  Returns the colour, the final
@@ -148,12 +189,12 @@ struct Resident {
 // With DEPTH it also composites the records' depths, D = sum d alpha T
 // (the depth form of the blending sum, Sec. 3.2), from s_depth.
 template <int B, bool HIST, bool DEPTH = false>
-__device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsRec *s_rec,
-                                             uint32_t *s_idx, uint16_t (*s_list)[B], float C[3], float &T,
+__device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsBatch<B> &s_rec,
+                                             uint32_t *s_idx, uint8_t (*s_list)[4][B], float C[3], float &T,
                                              int &last, float *hist, Resident &res, float *s_depth = nullptr,
                                              float *D = nullptr) {
   const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
-  const int wave = threadIdx.x >> 6;
+  const int wave = threadIdx.x >> 6, row = ((int)threadIdx.x & 63) >> 4;
   T = 1.0f;
   C[0] = C[1] = C[2] = 0.0f;
   bool done = !c.inside;
@@ -165,16 +206,22 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
     const int nb = (int)min((int64_t)B, c.end - b);
     load_batch(ws, b, nb, s_rec, s_idx, DEPTH ? s_depth : nullptr);
     __syncthreads();
-    const int cnt = strip_list<B>(s_rec, nb, c, s_list[wave]);
+    int cq[4];
+    const int cnt = sub_lists<B>(s_rec, nb, c, s_list[wave], cq);
+    const int kmax = max(max(cq[0], cq[1]), max(cq[2], cq[3]));  // the same in every lane
     __syncthreads();
     res.lo = b;
     res.nb = nb;
     res.cnt = cnt;
-    for (int k = 0; k < cnt && !done; k++) {
-      const int j = s_list[wave][k];
-      const LdsRec &R = s_rec[j];
+    const uint8_t *mine = s_list[wave][row];
+    // each 16-lane row walks its own sub-block's list; a row whose list is
+    // shorter idles (valid = false) while the others finish
+    for (int k = 0; k < kmax && !done; k++) {
+      const bool valid = k < cnt;
+      const int j = valid ? mine[k] : 0;
+      const LdsRec R = rec_at(s_rec, j);
       const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, o.alpha_max);
-      const bool hit = a.alpha >= o.alpha_min;
+      const bool hit = valid && a.alpha >= o.alpha_min;
       const float Tn = T * (1.0f - a.alpha);
       const bool stop = hit && Tn < o.T_min;
       const bool take = hit && !stop;
@@ -183,7 +230,7 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
       C[1] = __fmaf_rn(w, R.r2.y, C[1]);
       C[2] = __fmaf_rn(w, R.r2.z, C[2]);
       if (DEPTH) *D = __fmaf_rn(w, s_depth[j], *D);
-      if (HIST && !stop) hist[(b + j) * 256 + threadIdx.x] = take ? T : 0.0f;
+      if (HIST && valid && !stop) hist[(b + j) * 256 + threadIdx.x] = take ? T : 0.0f;
       T = take ? Tn : T;
       last = stop ? (int)(b + j - c.start) : last;
       stopped = stopped || stop;
@@ -207,8 +254,8 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
 // forward's last batch `res` is the first one needed here it is used as it
 // sits in LDS, culled lists included.
 template <int B, int RED, bool HIST>
-__device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsRec *s_rec,
-                                              uint32_t *s_idx, uint16_t (*s_list)[B], float (*s_acc)[9],
+__device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsBatch<B> &s_rec,
+                                              uint32_t *s_idx, uint8_t (*s_list)[4][B], float (*s_acc)[9],
                                               int *s_max, float T, int last, const float g[3],
                                               const float *hist, Resident res) {
   const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
@@ -246,18 +293,23 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
       if (RED >= 1)
         for (int e = threadIdx.x; e < nb * 9; e += blockDim.x) (&s_acc[0][0])[e] = 0.0f;
       __syncthreads();
-      cnt = strip_list<B>(s_rec, nb, c, s_list[wave]);
+      int cq[4];
+      cnt = sub_lists<B>(s_rec, nb, c, s_list[wave], cq);
       __syncthreads();
     }
     // entries at or past `top` contribute to no pixel
-    while (cnt > 0 && (int)s_list[wave][cnt - 1] >= nb_top) cnt--;
+    const uint8_t *mine = s_list[wave][(lane & 63) >> 4];
+    while (cnt > 0 && (int)mine[cnt - 1] >= nb_top) cnt--;
+    int kmax = max(cnt, __shfl_xor(cnt, 16));  // the longest of the wavefront's four row lists
+    kmax = max(kmax, __shfl_xor(kmax, 32));
     const int jj_last = active ? last - (int)(lo - c.start) : 0;  // this pixel's entries: jj < jj_last
-    for (int k = cnt - 1; k >= 0; k--) {
-      const int jj = s_list[wave][k];
+    for (int k = kmax - 1; k >= 0; k--) {
+      const bool valid = k < cnt;
+      const int jj = valid ? mine[k] : 0;
       const int64_t j = lo + jj;
-      const LdsRec &R = s_rec[jj];
+      const LdsRec R = rec_at(s_rec, jj);
       const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, o.alpha_max);
-      const bool contrib = jj < jj_last && a.alpha >= o.alpha_min;
+      const bool contrib = valid && jj < jj_last && a.alpha >= o.alpha_min;
       if (__ballot(contrib) == 0ull) continue;
       // Every lane evaluates the partials (all finite: alpha <= 0.99); the
       // non-contributing ones get zero weights, so they add exact zeros.
@@ -286,15 +338,21 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
       v[4] = -0.5f * gp * a.dy * a.dy;
       T = contrib ? Ti : T;
       if (RED == 0) {
-        float mine = 0.0f;
+        // row sums (each row holds its own entry), then lane 16 row + q of
+        // the row adds component q with one device atomic
 #pragma unroll
-        for (int q = 0; q < 9; q++) {
-          const float tot = __builtin_bit_cast(
-              float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wave_sum_lane63(v[q])), 63));
-          mine = lane == q ? tot : mine;
-        }
-        if (lane < 9 && mine != 0.0f)
-          unsafeAtomicAdd(&ws.grad2d[(int64_t)s_idx[jj] * kGrad2dStride + lane], mine);
+        for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0xB1>(v[q]);   // quad_perm [1,0,3,2]
+#pragma unroll
+        for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0x4E>(v[q]);   // quad_perm [2,3,0,1]
+#pragma unroll
+        for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0x141>(v[q]);  // row_half_mirror
+#pragma unroll
+        for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0x140>(v[q]);  // row_mirror
+        const int q = lane & 15;
+        float tot = v[0];
+#pragma unroll
+        for (int k2 = 1; k2 < 9; k2++) tot = q == k2 ? v[k2] : tot;
+        if (q < 9 && tot != 0.0f) unsafeAtomicAdd(&ws.grad2d[(int64_t)s_idx[jj] * kGrad2dStride + q], tot);
       } else if (RED == 1) {
         if (contrib) {
 #pragma unroll
@@ -385,9 +443,9 @@ __device__ __forceinline__ float block_sum_fixed(float x, float *s_w) {
 template <int TW, int TH, int B, bool HIST, bool DEPTH>
 __global__ __launch_bounds__(kBlock) void k_raster_fwd(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
                                                        float *images, int n_views, float *depth) {
-  __shared__ LdsRec s_rec[B];
+  __shared__ LdsBatch<B> s_rec;
   __shared__ float s_depth[DEPTH ? B : 1];
-  __shared__ uint16_t s_list[4][B];
+  __shared__ uint8_t s_list[4][4][B];  // [wavefront][sub-block][entry index in the batch]
   __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
   for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
   __syncthreads();
@@ -442,9 +500,9 @@ __global__ __launch_bounds__(kBlock) void k_l1(KWs ws, KOpts o, int64_t tile_lo,
 template <int TW, int TH, int B, int RED, bool HIST>
 __global__ __launch_bounds__(kBlock) void k_raster_bwd(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
                                                        const float *dLdC, int n_views) {
-  __shared__ LdsRec s_rec[B];
+  __shared__ LdsBatch<B> s_rec;
   __shared__ uint32_t s_idx[B];
-  __shared__ uint16_t s_list[4][B];
+  __shared__ uint8_t s_list[4][4][B];  // [wavefront][sub-block][entry index in the batch]
   __shared__ float s_acc[RED >= 1 ? B : 1][9];
   __shared__ int s_max;
   __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
@@ -476,9 +534,9 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(KWs ws, KOpts o, int64_t 
 template <int TW, int TH, int B, int RED, bool HIST>
 __global__ __launch_bounds__(kBlock) void k_fused(KWs ws, KOpts o, const float *targets, float *images,
                                                   int n_views, const uint32_t *order) {
-  __shared__ LdsRec s_rec[B];
+  __shared__ LdsBatch<B> s_rec;
   __shared__ uint32_t s_idx[B];
-  __shared__ uint16_t s_list[4][B];
+  __shared__ uint8_t s_list[4][4][B];  // [wavefront][sub-block][entry index in the batch]
   __shared__ float s_acc[RED >= 1 ? B : 1][9];
   __shared__ int s_max;
   __shared__ float s_w[4];
