@@ -129,7 +129,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else (8, 32)
+    tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else (16, 16)
     rb = Rasterizer(scene.n, scene.sh_degree, sizes, mode="batched", tile=tile, profile_stages=1,
                     lds_batch=args.lds_batch, grid_per_cu=args.grid_per_cu, bwd_reduce=args.bwd_reduce)
     rb.step_l1(params, cams, targets, stats=True)
