@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--tile", default=None, help="fixed tile shape WxH (with --no-autotune)")
     ap.add_argument("--lds-batch", type=int, default=256, help="with --no-autotune")
     ap.add_argument("--grid-per-cu", type=int, default=8, help="with --no-autotune")
-    ap.add_argument("--bwd-reduce", type=int, default=4, help="with --no-autotune")
+    ap.add_argument("--bwd-reduce", type=int, default=0, help="with --no-autotune")
     ap.add_argument("--order", choices=["morton", "random"], default="morton",
                     help="storage order of the Gaussians: Morton order of their means (the layout the framework "
                          "keeps), or the generator's random order")
@@ -139,7 +139,7 @@ def main():
     if not args.no_autotune:
         best, ms = rb.autotune(params, cams, targets, reps=2)
         log(f"autotune: tile {best.tile_w}x{best.tile_h}, lds_batch {best.lds_batch}, grid/CU "
-            f"{best.grid_per_cu}, bwd {best.bwd_variant}: {ms:.3f} ms")
+            f"{best.grid_per_cu}, bwd {best.bwd_variant}, reduction {best.bwd_reduce}: {ms:.3f} ms")
     opt = rb.options
 
     # ---- timed region: K replays of the captured batched step
@@ -469,6 +469,7 @@ def main():
                    "form": "batched fused fwd+L1+bwd with SD statistics, one HIP graph",
                    "tile": f"{opt.tile_w}x{opt.tile_h}", "lds_batch": opt.lds_batch,
                    "grid_per_cu": opt.grid_per_cu, "bwd_variant": "stored" if counts.bwd_variant == 2 else "recompute",
+                   "bwd_reduce": opt.bwd_reduce,
                    "gaussian_order": args.order},
         "gaussians_per_s": round(n * V / (ms_batched * 1e-3), 1),
         "visible_gaussian_views_per_s": round(vis / (ms_batched * 1e-3), 1),

@@ -92,8 +92,9 @@ typedef struct gsr_options {
   int32_t accumulate_grads; /* 0: gradients are overwritten; 1: added to */
   int32_t check_finite;  /* 1: flag non-finite parameters (GSR_ERR_NONFINITE via query) */
   int32_t profile_stages; /* 1: time every stage of eager calls with device events */
-  int32_t bwd_reduce;     /* reverse-pass reduction: 0 = wavefront DPP sums + one device atomic per
-                             (wavefront, record, component); 1 = per-lane LDS float atomics into a
+  int32_t bwd_reduce;     /* reverse-pass reduction (each 16-lane row of a wavefront walks its own
+                             entry list): 0 = a reduce-scatter over the row + one device atomic per
+                             (row, record, component); 1 = per-lane LDS float atomics into a
                              per-batch accumulator + one device atomic per (tile, record,
                              component); 2 = as 1 after DPP sums over lane quads; 3 = as 1 after
                              DPP sums over 16-lane rows, one LDS atomic instruction per entry;
@@ -169,7 +170,7 @@ typedef struct gsr_layout {
 typedef struct gsr_plan gsr_plan;
 
 /* Fills *opt with the defaults above (plain mode, 16x16 tiles, recompute backward,
- * LDS batch 128, 4 persistent workgroups per compute unit, reverse reduction 4). */
+ * LDS batch 128, 4 persistent workgroups per compute unit, reverse reduction 0). */
 void gsr_default_options(gsr_options *opt);
 
 /* Creates a plan for a static problem shape.  Host only (no device call).

@@ -441,7 +441,7 @@ void gsr_default_options(gsr_options *o) {
   o->bwd_variant = GSR_BWD_RECOMPUTE;
   o->lds_batch = 128;
   o->grid_per_cu = 4;
-  o->bwd_reduce = 4;
+  o->bwd_reduce = 0;
   o->accumulate_grads = 0;
   o->check_finite = 0;
   o->near_plane = 0.01f;

@@ -240,11 +240,44 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
   if (!stopped) last = c.inside ? (int)(c.end - c.start) : 0;
 }
 
+// Reduce-scatter of the nine partials over each 16-lane row: four butterfly
+// steps between lanes i and i ^ 7, i ^ 1, i ^ 2, i ^ 8 (row_half_mirror, two
+// quad permutations, row_ror:8), each step leaving a lane half of the
+// components it carried, summed with its partner's.  Lanes 0..8 of a row end
+// with the row sums of components 0, 2, 1, 3, 5, 7, 6, 8, 4 (comp_of_lane);
+// 27 operations where four full row sums and a select take 44.
+__device__ __forceinline__ float row_reduce_scatter(const float v[9], bool lb0, bool lb1, bool lb2, bool lb3) {
+  float r[5], t0, t1, u;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const float keep = lb2 ? v[k + 5] : v[k], send = lb2 ? v[k] : v[k + 5];
+    r[k] = keep + dpp_or_zero<0x141>(send);  // row_half_mirror: lane i ^ 7
+  }
+  r[4] = v[4] + dpp_or_zero<0x141>(v[4]);
+  float s3[3];
+#pragma unroll
+  for (int k = 0; k < 2; k++) {
+    const float keep = lb0 ? r[k + 2] : r[k], send = lb0 ? r[k] : r[k + 2];
+    s3[k] = keep + dpp_or_zero<0xB1>(send);  // quad_perm [1,0,3,2]: lane i ^ 1
+  }
+  s3[2] = r[4] + dpp_or_zero<0xB1>(r[4]);
+  {
+    const float keep = lb1 ? s3[1] : s3[0], send = lb1 ? s3[0] : s3[1];
+    t0 = keep + dpp_or_zero<0x4E>(send);  // quad_perm [2,3,0,1]: lane i ^ 2
+    t1 = s3[2] + dpp_or_zero<0x4E>(s3[2]);
+  }
+  {
+    const float keep = lb3 ? t1 : t0, send = lb3 ? t0 : t1;
+    u = keep + dpp_or_zero<0x128>(send);  // row_ror:8: lane i ^ 8
+  }
+  return u;
+}
+
 // Back-to-front reverse pass of one tile.  g = dL/dC_out of this lane's
 // pixel, T its final transmittance (recovered entry by entry unless the
 // forward stored it).
-//   RED = 0: per kept entry, DPP sums of the nine partials over the
-//            wavefront and one device atomic per component from lanes 0..8.
+//   RED = 0: per row entry, the reduce-scatter of the nine partials over the
+//            row and one device atomic per component from lanes 0..8.
 //   RED = 1: contributing lanes add their partials into an LDS accumulator
 //            of the batch (ds_add_f32, combining the four wavefronts); one
 //            device atomic per non-zero (entry, component) after the batch.
@@ -338,21 +371,11 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
       v[4] = -0.5f * gp * a.dy * a.dy;
       T = contrib ? Ti : T;
       if (RED == 0) {
-        // row sums (each row holds its own entry), then lane 16 row + q of
-        // the row adds component q with one device atomic
-#pragma unroll
-        for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0xB1>(v[q]);   // quad_perm [1,0,3,2]
-#pragma unroll
-        for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0x4E>(v[q]);   // quad_perm [2,3,0,1]
-#pragma unroll
-        for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0x141>(v[q]);  // row_half_mirror
-#pragma unroll
-        for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0x140>(v[q]);  // row_mirror
-        const int q = lane & 15;
-        float tot = v[0];
-#pragma unroll
-        for (int k2 = 1; k2 < 9; k2++) tot = q == k2 ? v[k2] : tot;
-        if (q < 9 && tot != 0.0f) unsafeAtomicAdd(&ws.grad2d[(int64_t)s_idx[jj] * kGrad2dStride + q], tot);
+        // the row's reduce-scatter, then one device atomic per component from
+        // lanes 0..8 of the row into its entry's gradient slot
+        const float u = row_reduce_scatter(v, lb0, lb1, lb2, lb3);
+        if (comp_of_lane >= 0 && u != 0.0f)
+          unsafeAtomicAdd(&ws.grad2d[(int64_t)s_idx[jj] * kGrad2dStride + comp_of_lane], u);
       } else if (RED == 1) {
         if (contrib) {
 #pragma unroll
@@ -379,35 +402,7 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
         for (int k = 1; k < 9; k++) mine = q == k ? v[k] : mine;
         if (q < 9 && mine != 0.0f) atomicAdd(&s_acc[jj][q], mine);
       } else if (RED == 4) {
-        // reduce-scatter over each 16-lane row: four butterfly steps between
-        // lanes i and i ^ 7, i ^ 1, i ^ 2, i ^ 8 (row_half_mirror, two quad
-        // permutations, row_ror:8), each step leaving a lane half of the
-        // components it carried, summed with its partner's; lanes 0..8 of a
-        // row end with the row sums of components 0, 2, 1, 3, 5, 7, 6, 8, 4
-        // (comp_of_lane), one LDS atomic instruction per entry
-        float r[5], t0, t1, u;
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-          const float keep = lb2 ? v[k + 5] : v[k], send = lb2 ? v[k] : v[k + 5];
-          r[k] = keep + dpp_or_zero<0x141>(send);  // row_half_mirror: lane i ^ 7
-        }
-        r[4] = v[4] + dpp_or_zero<0x141>(v[4]);
-        float s3[3];
-#pragma unroll
-        for (int k = 0; k < 2; k++) {
-          const float keep = lb0 ? r[k + 2] : r[k], send = lb0 ? r[k] : r[k + 2];
-          s3[k] = keep + dpp_or_zero<0xB1>(send);  // quad_perm [1,0,3,2]: lane i ^ 1
-        }
-        s3[2] = r[4] + dpp_or_zero<0xB1>(r[4]);
-        {
-          const float keep = lb1 ? s3[1] : s3[0], send = lb1 ? s3[0] : s3[1];
-          t0 = keep + dpp_or_zero<0x4E>(send);  // quad_perm [2,3,0,1]: lane i ^ 2
-          t1 = s3[2] + dpp_or_zero<0x4E>(s3[2]);
-        }
-        {
-          const float keep = lb3 ? t1 : t0, send = lb3 ? t0 : t1;
-          u = keep + dpp_or_zero<0x128>(send);  // row_ror:8: lane i ^ 8
-        }
+        const float u = row_reduce_scatter(v, lb0, lb1, lb2, lb3);
         if (comp_of_lane >= 0 && u != 0.0f) atomicAdd(&s_acc[jj][comp_of_lane], u);
       } else {
         // quad sums (two DPP steps), then one LDS atomic per quad and component
