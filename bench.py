@@ -37,9 +37,6 @@ FP32_PEAK_TFLOPS = 157.3
 # share (9) = 58.
 FLOPS_FWD_PAIR = 21
 FLOPS_BWD_PAIR = 58
-# Without packed FP32 instructions (the kernels are built with them disabled)
-# the vector issue ceiling is 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
-FP32_UNPACKED_TFLOPS = 78.6
 RASTER_SOURCES = ["paper_2510_01767_amd/csrc/gsr_raster.hip", "paper_2510_01767_amd/csrc/gsr_device.h",
                   "paper_2510_01767_amd/csrc/gsr_internal.h"]
 TRAFFIC_SUMMARY = "profiles/hbm_traffic_city-block-3000k-16views.md"
@@ -388,8 +385,7 @@ def main():
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": fused_traffic(opt) if args.config == 2 else None, "kernel": "k_fused",
-                "pairs": pairs, "flops_per_pair": FLOPS_FWD_PAIR + FLOPS_BWD_PAIR,
-                "frac_of_unpacked_fp32": round(achieved / FP32_UNPACKED_TFLOPS, 4)}
+                "pairs": pairs, "flops_per_pair": FLOPS_FWD_PAIR + FLOPS_BWD_PAIR}
     else:
         # per-Gaussian streams (project / project_bwd / emit / sort) are bound by HBM
         bytes_by_stage = {
