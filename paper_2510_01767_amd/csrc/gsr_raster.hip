@@ -4,21 +4,22 @@
 //
 // Work decomposition.  One workgroup (4 wavefronts, 256 lanes) owns one tile
 // of 256 pixels, one lane per pixel.  The tile's ordered entry list is
-// streamed through LDS in batches of B records.  Each wavefront then culls
-// the batch against its own 64-pixel strip: an entry is kept only if the
-// ellipse on which its alpha reaches alpha_min (its "reach", precomputed per
-// record) can touch a pixel centre of the strip.  Culled entries have
-// alpha < alpha_min at every pixel of the strip, so the result is identical
-// to evaluating them; on city-scale scenes most entries of a tile list miss
-// most strips, which is where the time would otherwise go.
+// streamed through LDS in batches of B records.  Each wavefront owns a
+// 64-pixel strip of the tile and each 16-lane row of it a 16-pixel
+// sub-block; the batch is culled against the strip, then against each
+// sub-block: an entry is kept for a sub-block only if the ellipse on which
+// its alpha reaches alpha_min (its "reach", precomputed per record) can
+// touch a pixel centre of the sub-block.  Each row then walks its own kept
+// list in depth order.  Culled entries have alpha < alpha_min at every pixel
+// they skip, so the result is identical to evaluating them; on city-scale
+// scenes most entries of a tile list miss most sub-blocks, which is where
+// the time would otherwise go.
 //
-// Reverse pass.  Two reductions of the nine 2D partials per entry, chosen by
-// the autotuner: DPP sums over the wavefront (skipped by ballot when no lane
-// contributes) with lanes 0..8 issuing one device atomic each into the
-// record's gradient slot (nine consecutive floats of one cache line); or LDS
-// float atomics into a per-batch accumulator that also combines the four
-// wavefronts, flushed with one device atomic per (entry, component), either
-// from every contributing lane or after DPP sums over lane quads.
+// Reverse pass.  Each row reduces the nine 2D partials of its entry by a
+// reduce-scatter over its 16 lanes; lanes 0..8 then either add the sums to
+// the record's gradient slot with device atomics, or (the other variants the
+// autotuner weighs) into a per-batch LDS accumulator flushed with one device
+// atomic per (entry, component).
 #include <hip/hip_runtime.h>
 
 #include "gsr_device.h"
