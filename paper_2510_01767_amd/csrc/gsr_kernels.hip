@@ -420,8 +420,10 @@ __global__ __launch_bounds__(kBlock) void k_emit(KWs ws, int64_t n, int n_views,
     if (q < ntiles) {
       const int dy = q / wx, dx = q - dy * wx;
       const int64_t t = vi.tile_base + (int64_t)(y0 + dy) * vi.tiles_x + (x0 + dx);
+      // rk[q] < the tile's count, so the slot lies in the tile's bucket; the
+      // capacity bound is what an overflowing step can break
       const uint64_t slot = (uint64_t)ws.tile_start[t] + rk[q];
-      if (slot < (uint64_t)ws.capacity && slot < (uint64_t)ws.tile_start[t + 1]) ws.keys[slot] = key;
+      if (slot < (uint64_t)ws.capacity) ws.keys[slot] = key;
     }
   }
   // the overflow entries of large footprints follow the ranked ones
