@@ -31,7 +31,9 @@ struct WsHeader {
   uint32_t queue;         // persistent raster work counter
   uint32_t union_count;   // Gaussians visible in >= 1 view
   uint32_t isect_total;
-  uint32_t pad[3];
+  uint32_t big_count;     // tiles whose lists exceed one wavefront's sort, collected per sort call
+  uint32_t big_next;      // their work counter
+  uint32_t pad;
   uint32_t isect[GSR_MAX_VIEWS];
   uint32_t visible[GSR_MAX_VIEWS];
   // longest-list-first schedule of the persistent raster: tiles per length

@@ -639,22 +639,34 @@ __device__ void sort_tile_block(const KWs &ws, int64_t t, uint64_t *s) {
 // lists the large ones in LDS and sorts them one after the other (the list
 // and its length are uniform per workgroup, so every thread reaches every
 // barrier).  Tiles this large are rare (dense spots of a view).
-__global__ __launch_bounds__(kSortBigThreads) void k_sort_big(KWs ws, int64_t tile_lo, int64_t tile_count) {
+// Tiles longer than one wavefront's register sort: collected into a list
+// (tile_order is free between the scan and the schedule), then sorted by
+// persistent 1024-thread workgroups that take them one at a time, so long
+// tiles spread over the whole chip.
+__global__ void k_big_reset(KWs ws) {
+  ws.hdr->big_count = 0u;
+  ws.hdr->big_next = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_big_collect(KWs ws, int64_t tile_lo, int64_t tile_count) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < tile_count;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = tile_lo + b;
+    if ((int64_t)ws.tile_start[t + 1] - ws.tile_start[t] > kWaveSortMax)
+      ws.tile_order[atomicAdd(&ws.hdr->big_count, 1u)] = (uint32_t)t;
+  }
+}
+
+__global__ __launch_bounds__(kSortBigThreads) void k_sort_big(KWs ws) {
   __shared__ uint64_t s[kSortLds];
-  __shared__ int64_t s_big[kSortBigThreads];
-  __shared__ int s_nbig;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < tile_count; base += (int64_t)gridDim.x * blockDim.x) {
-    if (threadIdx.x == 0) s_nbig = 0;
+  __shared__ uint32_t s_k;
+  const uint32_t count = ws.hdr->big_count;
+  for (;;) {
+    if (threadIdx.x == 0) s_k = atomicAdd(&ws.hdr->big_next, 1u);
     __syncthreads();
-    const int64_t b = base + threadIdx.x;
-    if (b < tile_count) {
-      const int64_t t = tile_lo + b;
-      if ((int64_t)ws.tile_start[t + 1] - ws.tile_start[t] > kWaveSortMax) s_big[atomicAdd(&s_nbig, 1)] = t;
-    }
-    __syncthreads();
-    const int nbig = s_nbig;
-    for (int k = 0; k < nbig; k++) sort_tile_block(ws, s_big[k], s);
-    __syncthreads();
+    const uint32_t k = s_k;
+    if (k >= count) break;
+    sort_tile_block(ws, ws.tile_order[k], s);  // ends with a barrier, before s_k is written again
   }
 }
 
@@ -1010,9 +1022,10 @@ int launch_sort(const KWs &ws, int64_t tile_lo, int64_t tile_count, void *stream
   hipLaunchKernelGGL(k_sort_wave<16>, wgrid, dim3(kBlock), 0, s, ws, tile_lo, tile_count, 0);
   hipLaunchKernelGGL(k_sort_wave<32>, wgrid, dim3(kBlock), 0, s, ws, tile_lo, tile_count, 1024);
   hipLaunchKernelGGL(k_sort_wave<64>, wgrid, dim3(kBlock), 0, s, ws, tile_lo, tile_count, 2048);
-  const int64_t bg = (tile_count + kSortBigThreads - 1) / kSortBigThreads;
-  hipLaunchKernelGGL(k_sort_big, dim3((unsigned)min(bg, (int64_t)4096)), dim3(kSortBigThreads), 0, s, ws, tile_lo,
-                     tile_count);
+  hipLaunchKernelGGL(k_big_reset, dim3(1), dim3(1), 0, s, ws);
+  hipLaunchKernelGGL(k_big_collect, dim3((unsigned)min((tile_count + kBlock - 1) / kBlock, (int64_t)4096)),
+                     dim3(kBlock), 0, s, ws, tile_lo, tile_count);
+  hipLaunchKernelGGL(k_sort_big, dim3(512), dim3(kSortBigThreads), 0, s, ws);
   return last_err();
 }
 
