@@ -153,7 +153,7 @@ __device__ __forceinline__ void load_batch(const KWs &ws, int64_t lo, int nb, Ld
 template <int B>
 __device__ __forceinline__ int sub_lists(const LdsBatch<B> &s_rec, int nb, const TileCtx &c, uint8_t (*lists)[B],
                                          int cnt[4]) {
-  static_assert(B <= 256, "byte indices");
+  static_assert(B <= 256 && (B & (B - 1)) == 0, "byte indices, masked by B - 1");
   const int lane = lane_id();
   const uint64_t below = (1ull << lane) - 1ull;
   cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0;
@@ -219,7 +219,9 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
     // shorter idles (valid = false) while the others finish
     for (int k = 0; k < kmax && !done; k++) {
       const bool valid = k < cnt;
-      const int j = valid ? mine[k] : 0;
+      // read unconditionally (no branch): past the row's count the byte is stale,
+      // masked into the batch and the pair marked invalid
+      const int j = mine[k] & (B - 1);
       const LdsRec R = rec_at(s_rec, j);
       const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, o.alpha_max);
       const bool hit = valid && a.alpha >= o.alpha_min;
@@ -339,7 +341,7 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
     const int jj_last = active ? last - (int)(lo - c.start) : 0;  // this pixel's entries: jj < jj_last
     for (int k = kmax - 1; k >= 0; k--) {
       const bool valid = k < cnt;
-      const int jj = valid ? mine[k] : 0;
+      const int jj = mine[k] & (B - 1);  // as in the forward pass
       const int64_t j = lo + jj;
       const LdsRec R = rec_at(s_rec, jj);
       const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, o.alpha_max);
