@@ -153,7 +153,7 @@ __device__ __forceinline__ void load_batch(const KWs &ws, int64_t lo, int nb, Ld
 template <int B>
 __device__ __forceinline__ int sub_lists(const LdsBatch<B> &s_rec, int nb, const TileCtx &c, uint8_t (*lists)[B],
                                          int cnt[4]) {
-  static_assert(B <= 256 && (B & (B - 1)) == 0, "byte indices, masked by B - 1");
+  static_assert(B <= 256, "byte indices");
   const int lane = lane_id();
   const uint64_t below = (1ull << lane) - 1ull;
   cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0;
@@ -195,6 +195,8 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
                                              int &last, float *hist, Resident &res, float *s_depth = nullptr,
                                              float *D = nullptr) {
   const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
+  // canonical once, so the per-pair min needs no quieting of it
+  const float amax = __builtin_canonicalizef(o.alpha_max);
   const int wave = threadIdx.x >> 6, row = ((int)threadIdx.x & 63) >> 4;
   T = 1.0f;
   C[0] = C[1] = C[2] = 0.0f;
@@ -219,11 +221,11 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
     // shorter idles (valid = false) while the others finish
     for (int k = 0; k < kmax && !done; k++) {
       const bool valid = k < cnt;
-      // read unconditionally (no branch): past the row's count the byte is stale,
-      // masked into the batch and the pair marked invalid
-      const int j = mine[k] & (B - 1);
+      // past the row's count the list byte is stale and may name an entry the
+      // batch did not load: take entry 0 (always loaded) instead
+      const int j = valid ? mine[k] : 0;
       const LdsRec R = rec_at(s_rec, j);
-      const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, o.alpha_max);
+      const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, amax);
       const bool hit = valid && a.alpha >= o.alpha_min;
       const float Tn = T * (1.0f - a.alpha);
       const bool stop = hit && Tn < o.T_min;
@@ -295,6 +297,7 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
                                               int *s_max, float T, int last, const float g[3],
                                               const float *hist, Resident res) {
   const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
+  const float amax = __builtin_canonicalizef(o.alpha_max);  // as in the forward pass
   const int wave = threadIdx.x >> 6, lane = lane_id();
   // the reduce-scatter's lane roles (RED = 4): which component lane q of a
   // 16-lane row ends with, -1 for none
@@ -341,10 +344,10 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
     const int jj_last = active ? last - (int)(lo - c.start) : 0;  // this pixel's entries: jj < jj_last
     for (int k = kmax - 1; k >= 0; k--) {
       const bool valid = k < cnt;
-      const int jj = mine[k] & (B - 1);  // as in the forward pass
+      const int jj = valid ? mine[k] : 0;  // as in the forward pass
       const int64_t j = lo + jj;
       const LdsRec R = rec_at(s_rec, jj);
-      const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, o.alpha_max);
+      const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, amax);
       const bool contrib = valid && jj < jj_last && a.alpha >= o.alpha_min;
       if (__ballot(contrib) == 0ull) continue;
       // Every lane evaluates the partials (all finite: alpha <= 0.99); the
@@ -377,7 +380,7 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
         // the row's reduce-scatter, then one device atomic per component from
         // lanes 0..8 of the row into its entry's gradient slot
         const float u = row_reduce_scatter(v, lb0, lb1, lb2, lb3);
-        if (comp_of_lane >= 0 && u != 0.0f)
+        if (valid && comp_of_lane >= 0 && u != 0.0f)
           unsafeAtomicAdd(&ws.grad2d[(int64_t)s_idx[jj] * kGrad2dStride + comp_of_lane], u);
       } else if (RED == 1) {
         if (contrib) {
@@ -403,10 +406,10 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
         float mine = v[0];
 #pragma unroll
         for (int k = 1; k < 9; k++) mine = q == k ? v[k] : mine;
-        if (q < 9 && mine != 0.0f) atomicAdd(&s_acc[jj][q], mine);
+        if (valid && q < 9 && mine != 0.0f) atomicAdd(&s_acc[jj][q], mine);
       } else if (RED == 4) {
         const float u = row_reduce_scatter(v, lb0, lb1, lb2, lb3);
-        if (comp_of_lane >= 0 && u != 0.0f) atomicAdd(&s_acc[jj][comp_of_lane], u);
+        if (valid && comp_of_lane >= 0 && u != 0.0f) atomicAdd(&s_acc[jj][comp_of_lane], u);
       } else {
         // quad sums (two DPP steps), then one LDS atomic per quad and component
 #pragma unroll
@@ -415,7 +418,7 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
         for (int q = 0; q < 9; q++) v[q] += dpp_or_zero<0x4E>(v[q]);  // quad_perm [2,3,0,1]
 #pragma unroll
         for (int q = 0; q < 9; q++)
-          if ((lane & 3) == 0 && v[q] != 0.0f) atomicAdd(&s_acc[jj][q], v[q]);
+          if (valid && (lane & 3) == 0 && v[q] != 0.0f) atomicAdd(&s_acc[jj][q], v[q]);
       }
     }
     if (RED >= 1) {
