@@ -332,9 +332,9 @@ __device__ __forceinline__ PairAlpha pair_alpha(float pxc, float pyc, const floa
   const float e = __builtin_amdgcn_exp2f(p2);
   a.G = (p2 > 0.0f || p2 < pmin2) ? -1.0f : e;  // G < 0 marks a skipped pair
   a.raw = r1.w * a.G;
-  // min(raw, alpha_max) as one v_med3_f32 (the median of raw, alpha_max,
-  // alpha_max), without the quieting a minnum of a non-canonical operand takes
-  a.alpha = __builtin_amdgcn_fmed3f(a.raw, alpha_max, alpha_max);
+  // min(raw, alpha_max) as one v_med3_f32: the median of raw, alpha_max and
+  // -inf, without the quieting a minnum of a non-canonical operand takes
+  a.alpha = __builtin_amdgcn_fmed3f(a.raw, alpha_max, -__builtin_huge_valf());
   return a;
 }
 
