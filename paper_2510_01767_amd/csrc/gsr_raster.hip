@@ -222,8 +222,9 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
     for (int k = 0; k < kmax && !done; k++) {
       const bool valid = k < cnt;
       // past the row's count the list byte is stale and may name an entry the
-      // batch did not load: take entry 0 (always loaded) instead
-      const int j = valid ? mine[k] : 0;
+      // batch did not load: clamped into the loaded entries (no branch), the
+      // pair marked invalid
+      const int j = min((int)mine[k], nb - 1);
       const LdsRec R = rec_at(s_rec, j);
       const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, amax);
       const bool hit = valid && a.alpha >= o.alpha_min;
@@ -344,7 +345,7 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
     const int jj_last = active ? last - (int)(lo - c.start) : 0;  // this pixel's entries: jj < jj_last
     for (int k = kmax - 1; k >= 0; k--) {
       const bool valid = k < cnt;
-      const int jj = valid ? mine[k] : 0;  // as in the forward pass
+      const int jj = min((int)mine[k], nb - 1);  // as in the forward pass
       const int64_t j = lo + jj;
       const LdsRec R = rec_at(s_rec, jj);
       const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, amax);
