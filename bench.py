@@ -92,7 +92,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (blocks train independently, one "
+        print("bench.py measures one GPU: the framework has no multi-GPU path (blocks train independently, one "
               "GPU each); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

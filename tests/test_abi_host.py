@@ -183,3 +183,15 @@ def test_adam_step_rejects_bad_arguments_before_touching_the_device():
     assert L.gsr_adam_step(plan, ctypes.byref(hp), ctypes.byref(null), ctypes.byref(g), ctypes.byref(g),
                            ctypes.byref(g), None, None) == C.GSR_ERR_INVALID_ARG
     C.gsr_plan_destroy(plan)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: asking for more exits non-zero with a message, before any device use."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
