@@ -109,13 +109,13 @@ _C = ctypes.POINTER(Cam)
 def _declare(L):
     L.ora_sh_basis.argtypes = [ctypes.c_int, _d, _d, _d]
     L.ora_project.argtypes = [_O, _C, ctypes.c_int64, ctypes.c_int, _d, _d, _d, _d, _d, _u8,
-                              _i32, _d, _d, _d, _d, _d, _d, _d, _i32, _i32, _i32, _d, _d]
+                              _i32, _d, _d, _d, _d, _d, _d, _d, _i32, _i32, _i32, _d, _d, _d, _d]
     L.ora_bin.restype = ctypes.c_int64
     L.ora_bin.argtypes = [ctypes.c_int64, _i32, _i32, _u32, _i64, _i64, _i32, ctypes.c_int64,
                           ctypes.c_int64, _i64, _u32, _i64, _i64]
     L.ora_render.argtypes = [_O, ctypes.c_int32, ctypes.c_int32, _i64, _i64, ctypes.c_int64,
-                             _d, _d, _d, _d, _d, _u8, ctypes.c_double, ctypes.c_double, _d, _d, _i32, _d,
-                             _u8, _i64]
+                             _d, _d, _d, _d, _d, _u8, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                             _d, _d, _i32, _d, _u8, _i64]
     L.ora_render_brute.argtypes = [_O, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _i32, _i32,
                                    _u32, _i64, _d, _d, _d, _d, _d, _d, _d, _i32]
     L.ora_render_bwd.argtypes = [_O, ctypes.c_int32, ctypes.c_int32, _i64, _i64, ctypes.c_int64,
@@ -185,7 +185,7 @@ def project(P: Params, cam: dict, opts: Opts, keep=None) -> dict:
         cov2d=np.zeros((3, n)), depth=np.zeros(n), opacity=np.zeros(n),
         color=np.zeros((3, n)), color_raw=np.zeros((3, n)), radius=np.zeros(n, np.int32),
         rect=np.zeros((4, n), np.int32), ntiles=np.zeros(n, np.int32),
-        margin=np.zeros(n), grad_margin=np.zeros(n),
+        margin=np.zeros(n), grad_margin=np.zeros(n), depth_margin=np.zeros(n), color_margin=np.zeros(n),
     )
     c = make_cam(cam)
     kp = None if keep is None else np.ascontiguousarray(keep, np.uint8)
@@ -194,7 +194,8 @@ def project(P: Params, cam: dict, opts: Opts, keep=None) -> dict:
                       _p(P.sh, _d), _p(kp, _u8),
                       *[_p(out[k], _i32 if out[k].dtype == np.int32 else _d) for k in (
                           "visible", "mean2d", "conic", "cov2d", "depth", "opacity", "color",
-                          "color_raw", "radius", "rect", "ntiles", "margin", "grad_margin")])
+                          "color_raw", "radius", "rect", "ntiles", "margin", "grad_margin",
+                          "depth_margin", "color_margin")])
     return out
 
 
@@ -232,16 +233,27 @@ def _records_view(recs):
     """Concatenate per-view record dicts into planes indexed by r = v*n + i."""
     cat = lambda k: np.ascontiguousarray(np.concatenate([r[k] for r in recs], axis=-1))
     return {k: cat(k) for k in ("mean2d", "conic", "opacity", "color", "depth", "visible",
-                                "rect", "margin", "grad_margin")}
+                                "rect", "margin", "grad_margin", "depth_margin", "color_margin")}
 
 
 DELTA_GAUSS = 1e-9   # per-Gaussian decisions: both sides evaluate them in float64
 DELTA_ALPHA = 4e-6   # alpha thresholds: a float32 alpha carries <= ~1.5e-6 relative error
 DELTA_T = 2e-5       # stop decision: float32 transmittance after ~1000 factors
+# float32 rounding of a depth computed in float64 on both sides: the two
+# float64 values differ by a few units of 1e-16, so only depths within 1e-12
+# of a rounding boundary can round apart (a wider band would flag a few per
+# cent of all records, the boundaries being 6e-8 apart)
+DELTA_DEPTH_ROUND = 1e-12
+# two consecutive entries that may blend into a pixel, with float64 depths
+# this close, could be ordered the other way by another float64 evaluation
+DELTA_DEPTH_GAP = DELTA_GAUSS
+# colour clamp at 0: the colour is a float32 sum of up to 16 SH terms per
+# channel, accurate to ~1e-7 of max(1, |sum|)
+DELTA_COLOR = 1e-6
 
 
 def forward(P: Params, cams: list, opts: Opts, keep=None, delta=DELTA_GAUSS, delta_alpha=DELTA_ALPHA,
-            delta_T=DELTA_T) -> dict:
+            delta_T=DELTA_T, delta_depth_round=DELTA_DEPTH_ROUND, delta_depth_gap=DELTA_DEPTH_GAP) -> dict:
     """Full multi-view forward: records, binning, per-pixel compositing.
 
     delta* are the relative margins below which a discrete decision is called
@@ -259,7 +271,11 @@ def forward(P: Params, cams: list, opts: Opts, keep=None, delta=DELTA_GAUSS, del
     tile_base = np.repeat(tile_base_v, n)
     tiles_x = np.repeat(np.array([g[0] for g in grids], np.int32), n)
     bins = bin_records(R["rect"], R["visible"], depth_bits, tiebreak, tile_base, tiles_x, T_total)
-    rec_amb = np.ascontiguousarray((R["margin"] < delta).astype(np.uint8))
+    # bit 0: a decision of the record's own may go the other way; bit 1: the
+    # float32 rounding of its depth may (which matters only next to an entry
+    # of the same or an adjacent float32 depth)
+    rec_amb = np.ascontiguousarray((R["margin"] < delta).astype(np.uint8)
+                                   | (2 * (R["depth_margin"] < delta_depth_round)).astype(np.uint8))
     nr = n * V
     images, Tf, last, D, amb, sigs = [], [], [], [], [], []
     L = lib()
@@ -275,6 +291,7 @@ def forward(P: Params, cams: list, opts: Opts, keep=None, delta=DELTA_GAUSS, del
         L.ora_render(ctypes.byref(opts), W, H, _p(rv, _i64), _p(bins["values"], _i64), nr,
                      _p(R["mean2d"], _d), _p(R["conic"], _d), _p(R["opacity"], _d),
                      _p(R["color"], _d), _p(R["depth"], _d), _p(rec_amb, _u8), delta_alpha, delta_T,
+                     delta_depth_gap,
                      _p(img, _d), _p(t, _d), _p(la, _i32), _p(d, _d), _p(a, _u8), _p(sg, _i64))
         # A Gaussian whose own decisions are ambiguous may be listed in one
         # more tile row or column by another implementation: mark the pixels
@@ -308,6 +325,44 @@ def forward(P: Params, cams: list, opts: Opts, keep=None, delta=DELTA_GAUSS, del
     return dict(records=recs, R=R, bins=bins, images=images, T_final=Tf, last=last, depth=D,
                 ambiguous=amb, signature=sigs, tile_base=tile_base_v, tiles_per_view=tiles_per_view, grids=grids,
                 depth_bits=depth_bits)
+
+
+def touching(fwd: dict, flagged: list, opts: Opts) -> np.ndarray:
+    """Records whose FP64 alpha at a flagged pixel is at least alpha_min / 2.
+
+    fwd: the output of forward(); flagged: one bool [H][W] mask per view of
+    fwd's cameras.  Every entry of a flagged pixel's tile list is tested, past
+    the stop too.  A record below alpha_min / 2 at a pixel stays below
+    alpha_min under any float32 evaluation (relative error ~1e-6), so it takes
+    no part in that pixel's compositing on any correct implementation; the
+    others may.  Returns a bool array over record ids v * n + i."""
+    R = fwd["R"]
+    nr = R["visible"].shape[0]
+    out = np.zeros(nr, bool)
+    vals_all = fwd["bins"]["values"]
+    ranges = fwd["bins"]["ranges"]
+    thr = 0.5 * opts.alpha_min
+    for v, mask in enumerate(flagged):
+        ys, xs = np.nonzero(np.asarray(mask, bool))
+        if ys.size == 0:
+            continue
+        gx, _ = fwd["grids"][v]
+        t = (ys // opts.tile_h) * gx + xs // opts.tile_w
+        order = np.argsort(t, kind="stable")
+        t, ys, xs = t[order], ys[order], xs[order]
+        cuts = np.flatnonzero(np.diff(t)) + 1
+        for a, b in zip(np.concatenate([[0], cuts]), np.concatenate([cuts, [t.size]])):
+            s, e = ranges[fwd["tile_base"][v] + t[a]]
+            if e <= s:
+                continue
+            r = vals_all[s:e]
+            dx = (xs[a:b] + 0.5)[None, :] - R["mean2d"][0, r][:, None]
+            dy = (ys[a:b] + 0.5)[None, :] - R["mean2d"][1, r][:, None]
+            A, B, Cc = R["conic"][0, r][:, None], R["conic"][1, r][:, None], R["conic"][2, r][:, None]
+            p = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy
+            al = R["opacity"][r][:, None] * np.exp(np.minimum(p, 0.0))
+            out[r[(al >= thr).any(axis=1)]] = True
+    return out
 
 
 def l1_loss(images, targets):

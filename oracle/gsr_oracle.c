@@ -21,11 +21,12 @@
  * concurrently; it does not change any arithmetic.
  *
  * Guard band.  Every discrete decision (near/far, det > 0, the ceil of the
- * radius, the floors of the tile rectangle, alpha >= alpha_min,
- * o*G >= alpha_max, T*(1-alpha) < T_min) records its relative margin; a
- * float32 implementation may legitimately decide the other way when the
- * margin is tiny, so callers exclude such Gaussians and pixels from strict
- * comparison.
+ * radius, the floors of the tile rectangle, the float32 rounding of the depth
+ * that orders a tile's list, the colour clamp, alpha >= alpha_min,
+ * o*G >= alpha_max, T*(1-alpha) < T_min, and the order of two entries whose
+ * depths nearly coincide) records its relative margin; a float32
+ * implementation may legitimately decide the other way when the margin is
+ * tiny, so callers exclude such Gaussians and pixels from strict comparison.
  */
 #include <math.h>
 #include <stdint.h>
@@ -141,7 +142,20 @@ typedef struct {
   int radius, rect[4], visible, ntiles;
   double opacity, dirn[3], dnorm, Y[ORA_MAX_SH], color_raw[3], color[3];
   double margin, grad_margin;
+  double depth_margin; /* distance of the depth to a float32 rounding boundary, relative */
+  double color_margin; /* distance of the raw colour to the clamp at 0, relative */
 } ora_fwd;
+
+/* Relative distance of v to the nearest point where its rounding to float32
+ * changes: the midpoints between the float32 value nearest v and its two
+ * neighbours. */
+static double f32_round_margin(double v) {
+  float f = (float)v;
+  double up = 0.5 * ((double)f + (double)nextafterf(f, INFINITY));
+  double dn = 0.5 * ((double)f + (double)nextafterf(f, -INFINITY));
+  double d = fmin(fabs(v - up), fabs(v - dn));
+  return d / fmax(fabs(v), 1e-300);
+}
 
 static void project_one(const ora_opts *o, const ora_cam *cam, int sh_degree, const double mu[3],
                         const double ls[3], const double qr[4], double logit,
@@ -149,6 +163,8 @@ static void project_one(const ora_opts *o, const ora_cam *cam, int sh_degree, co
   memset(f, 0, sizeof *f);
   f->margin = INFINITY;
   f->grad_margin = INFINITY;
+  f->depth_margin = INFINITY;
+  f->color_margin = INFINITY;
   /* activations */
   for (int a = 0; a < 3; a++) f->s[a] = exp(ls[a]);
   f->qn = sqrt(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
@@ -171,6 +187,8 @@ static void project_one(const ora_opts *o, const ora_cam *cam, int sh_degree, co
   }
   memcpy(f->Wc, cam->R, sizeof f->Wc);
   double tz = f->tc[2];
+  /* the list order compares depths as float32 bit patterns */
+  f->depth_margin = f32_round_margin(tz);
   f->margin = fmin(f->margin, fabs(tz - o->near_plane) / fmax(fabs(tz), 1e-300));
   f->margin = fmin(f->margin, rel_margin(tz, o->far_plane));
   if (!(tz > o->near_plane && tz < o->far_plane)) {
@@ -258,7 +276,7 @@ static void project_one(const ora_opts *o, const ora_cam *cam, int sh_degree, co
     for (int k = 0; k < K; k++) acc += shv[k * 3 + ch] * f->Y[k];
     f->color_raw[ch] = acc + 0.5;
     f->color[ch] = f->color_raw[ch] > 0 ? f->color_raw[ch] : 0.0;
-    f->grad_margin = fmin(f->grad_margin, fabs(f->color_raw[ch]) / fmax(1.0, fabs(acc)));
+    f->color_margin = fmin(f->color_margin, fabs(f->color_raw[ch]) / fmax(1.0, fabs(acc)));
   }
 }
 
@@ -272,7 +290,8 @@ void ora_project(const ora_opts *o, const ora_cam *cam, int64_t n, int sh_degree
                  const double *logits, const double *sh, const uint8_t *keep,
                  int32_t *visible, double *mean2d, double *conic, double *cov2d, double *depth,
                  double *opacity, double *color, double *color_raw, int32_t *radius, int32_t *rect,
-                 int32_t *ntiles, double *margin, double *grad_margin) {
+                 int32_t *ntiles, double *margin, double *grad_margin, double *depth_margin,
+                 double *color_margin) {
   int K = (sh_degree + 1) * (sh_degree + 1);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; i++) {
@@ -294,6 +313,8 @@ void ora_project(const ora_opts *o, const ora_cam *cam, int64_t n, int sh_degree
     ntiles[i] = f.ntiles;
     margin[i] = f.margin;
     grad_margin[i] = f.grad_margin;
+    depth_margin[i] = f.depth_margin;
+    color_margin[i] = f.color_margin;
   }
 }
 
@@ -362,7 +383,12 @@ int64_t ora_bin(int64_t n_rec, const int32_t *rect /* [4][n_rec] */, const int32
  * Records are planes indexed by record id: mean2d [2][nr], conic [3][nr],
  * opacity [nr], color [3][nr], depth [nr].  A pixel is marked ambiguous when
  * an alpha decision has relative margin below delta, the stop decision one
- * below delta_T, or a record flagged ambiguous could blend into it.
+ * below delta_T, a record flagged ambiguous (rec_amb bit 0) could blend into
+ * it, or two entries that may blend into it (alpha within delta of
+ * alpha_min or above) follow each other in an order another evaluation could
+ * flip: depths closer than delta_depth relative, or float32 depths at most
+ * one unit in the last place apart where one of the two records has a depth
+ * whose float32 rounding is itself ambiguous (rec_amb bit 1).
  */
 typedef struct {
   int64_t nr;
@@ -371,10 +397,12 @@ typedef struct {
 } ora_records;
 
 static int composite_pixel(const ora_opts *o, const ora_records *rc, const int64_t *vals,
-                           int64_t len, double px, double py, double delta, double delta_T, double C[3], double *D,
-                           double *Tout, int *amb, double *alpha_hist, double *T_hist,
-                           int64_t *sig) {
+                           int64_t len, double px, double py, double delta, double delta_T,
+                           double delta_depth, double C[3], double *D, double *Tout, int *amb,
+                           double *alpha_hist, double *T_hist, int64_t *sig) {
   double T = 1.0;
+  double prev_depth = NAN; /* depth of the last entry that may blend into this pixel */
+  int64_t prev_r = -1;
   C[0] = C[1] = C[2] = 0;
   *D = 0;
   *amb = 0;
@@ -390,8 +418,18 @@ static int composite_pixel(const ora_opts *o, const ora_records *rc, const int64
     if (p > 0) continue;
     double raw = rc->opacity[r] * exp(p);
     /* a record with an ambiguous decision of its own matters where it could blend */
-    if (rc->rec_amb && rc->rec_amb[r] && raw >= 0.5 * o->alpha_min) *amb = 1;
+    if (rc->rec_amb && (rc->rec_amb[r] & 1) && raw >= 0.5 * o->alpha_min) *amb = 1;
     if (rel_margin(raw, o->alpha_min) < delta || rel_margin(raw, o->alpha_max) < delta) *amb = 1;
+    if (raw >= o->alpha_min * (1.0 - delta)) {
+      double dep = rc->depth[r];
+      if (fabs(dep - prev_depth) < delta_depth * fabs(dep)) *amb = 1; /* false while prev_depth is NaN */
+      if (prev_r >= 0 && rc->rec_amb && ((rc->rec_amb[r] | rc->rec_amb[prev_r]) & 2)) {
+        float a = (float)dep, b = (float)prev_depth;
+        if (a == b || nextafterf(b, INFINITY) == a || nextafterf(b, -INFINITY) == a) *amb = 1;
+      }
+      prev_depth = dep;
+      prev_r = r;
+    }
     double alpha = raw < o->alpha_max ? raw : o->alpha_max;
     if (alpha < o->alpha_min) continue;
     double Tn = T * (1.0 - alpha);
@@ -413,7 +451,8 @@ static int composite_pixel(const ora_opts *o, const ora_records *rc, const int64
 void ora_render(const ora_opts *o, int32_t W, int32_t H, const int64_t *ranges_view,
                 const int64_t *values, int64_t nr, const double *mean2d, const double *conic,
                 const double *opacity, const double *color, const double *depth,
-                const uint8_t *rec_amb, double delta, double delta_T, double *image, double *T_final,
+                const uint8_t *rec_amb, double delta, double delta_T, double delta_depth, double *image,
+                double *T_final,
                 int32_t *last, double *depth_out, uint8_t *ambiguous, int64_t *signature) {
   ora_records rc = {nr, mean2d, conic, opacity, color, depth, rec_amb};
   int tiles_x = (W + o->tile_w - 1) / o->tile_w;
@@ -426,7 +465,8 @@ void ora_render(const ora_opts *o, int32_t W, int32_t H, const int64_t *ranges_v
     double C[3], D, T;
     int amb;
     int64_t sg;
-    int n = composite_pixel(o, &rc, values + s, e - s, px, py, delta, delta_T, C, &D, &T, &amb, NULL, NULL, &sg);
+    int n = composite_pixel(o, &rc, values + s, e - s, px, py, delta, delta_T, delta_depth, C, &D, &T, &amb, NULL,
+                            NULL, &sg);
     for (int ch = 0; ch < 3; ch++) image[ch * P + pix] = C[ch] + T * o->bg[ch];
     T_final[pix] = T;
     last[pix] = n;
@@ -473,7 +513,7 @@ void ora_render_brute(const ora_opts *o, int32_t W, int32_t H, int64_t nr, const
     for (int64_t k = 0; k < m; k++) vals[k] = list[k].rec;
     double C[3], D, T;
     int amb;
-    int n = composite_pixel(o, &rc, vals, m, px, py, 0.0, 0.0, C, &D, &T, &amb, NULL, NULL, NULL);
+    int n = composite_pixel(o, &rc, vals, m, px, py, 0.0, 0.0, 0.0, C, &D, &T, &amb, NULL, NULL, NULL);
     for (int ch = 0; ch < 3; ch++) image[ch * P + pix] = C[ch] + T * o->bg[ch];
     T_final[pix] = T;
     last[pix] = n;
@@ -510,7 +550,7 @@ void ora_render_bwd(const ora_opts *o, int32_t W, int32_t H, const int64_t *rang
     double *ah = malloc(sizeof(double) * len), *th = malloc(sizeof(double) * len);
     double C[3], D, T;
     int amb;
-    int n = composite_pixel(o, &rc, values + s, len, px, py, 0.0, 0.0, C, &D, &T, &amb, ah, th, NULL);
+    int n = composite_pixel(o, &rc, values + s, len, px, py, 0.0, 0.0, 0.0, C, &D, &T, &amb, ah, th, NULL);
     double g[3] = {dL_dimg[pix], dL_dimg[P + pix], dL_dimg[2 * P + pix]};
     double Bacc[3] = {T * o->bg[0], T * o->bg[1], T * o->bg[2]};
     for (int j = n - 1; j >= 0; j--) {

@@ -6,11 +6,13 @@ decisions are not ambiguous, and relative L2 <= 1e-5 over whole images);
 gradients within 1e-3 relative per parameter group (relative L2) and per
 element |gpu - ora| <= 1e-3 (|ora| + 1e-2 rms_group).  A decision is
 ambiguous when its FP64 relative margin is below the oracle's guard (per
-Gaussian: 1e-9, both sides decide in float64; per pair: 4e-6 for the alpha
-thresholds and 2e-5 for the stop, bounds on the float32 error of alpha and
-of the transmittance); another correct implementation may take it either
-way, so such pixels (and the Gaussians touching them) are left out of the
-per-element checks and counted.
+Gaussian: 1e-9, both sides decide in float64, and 1e-12 for the float32
+rounding of the depth; per pair: 4e-6 for the alpha thresholds and 2e-5 for
+the stop, bounds on the float32 error of alpha and of the transmittance;
+1e-9 between the depths of consecutive entries); another correct
+implementation may take it either way, so such pixels, and the Gaussians
+whose alpha reaches alpha_min / 2 at them, are left out of the per-element
+checks and counted.
 """
 import numpy as np
 import torch
@@ -56,7 +58,7 @@ def compare_images(gpu_images, ora, report=None):
         assert rel <= IMG_TOL, (v, rel)
     if report is not None:
         report.update(ambiguous_pixels=n_amb, pixels=n_pix, image_max_rel=worst)
-    assert n_amb <= 1e-3 * n_pix + 200, (n_amb, n_pix)
+    assert n_amb <= AMB_RATE * n_pix + AMB_FLOOR * len(ora["images"]), (n_amb, n_pix)
     return worst
 
 
@@ -70,35 +72,92 @@ def compare_pixels(gpu_T, gpu_last, ora):
 
 
 L1_KINK = 1e-5  # |image - target| below this: the L1 sign may differ (float32 image error ~1e-6)
+# Ambiguous pixels allowed per view: a rate of 1e-4 plus a floor for tiny
+# views.  The rate follows from the alpha guard band: a float32 alpha is
+# within ~1.5e-6 of the FP64 one, so a band of 4e-6 around alpha_min is the
+# narrowest that covers it, and at ~300 list entries per pixel it flags
+# about 1e-4 of the pixels.
+AMB_RATE = 1e-4
+AMB_FLOOR = 8
+# Largest fraction of the checked Gaussians the exclusions may remove; the
+# small dense test scenes (a hundred Gaussians per pixel on a few thousand
+# pixels) lose more per flagged pixel.
+MAX_EXCLUDED = 0.05
+MAX_EXCLUDED_DENSE = 0.25
+
+
+def record_ambiguous(rec):
+    """Per-record decisions another implementation may take the other way:
+    the float64 ones (culling, determinant, radius, rectangle).  The float32
+    rounding of the depth is handled per pixel by the oracle (it matters only
+    next to an entry of the same or an adjacent float32 depth)."""
+    return rec["margin"] < DELTA
+
+
+def depth_round_ambiguous(rec):
+    return rec["depth_margin"] < oracle.DELTA_DEPTH_ROUND
+
+
+def unambiguous_tiles(ora):
+    """Tiles whose list order no correct implementation can change: no listed
+    record has an ambiguous decision of its own, and no record whose depth
+    may round to another float32 value sits next to an entry of the same or
+    an adjacent float32 depth."""
+    b = ora["bins"]
+    R = ora["R"]
+    own = R["margin"] < DELTA
+    rnd = R["depth_margin"] < oracle.DELTA_DEPTH_ROUND
+    ok = np.ones(b["ranges"].shape[0], bool)
+    vals = b["values"]
+    if vals.size == 0:
+        return ok
+    tile_of = np.repeat(np.arange(ok.size), b["ranges"][:, 1] - b["ranges"][:, 0])
+    ok[np.unique(tile_of[own[vals]])] = False
+    bits = b["depth"].astype(np.int64)
+    near = (np.abs(np.diff(bits)) <= 1) & (tile_of[1:] == tile_of[:-1]) & (rnd[vals[1:]] | rnd[vals[:-1]])
+    ok[np.unique(tile_of[1:][near])] = False
+    return ok
+
+
+def flagged_pixels(ora, targets=None):
+    """Per view, the pixels whose discrete decisions are ambiguous, plus (given
+    the targets) the pixels on the L1 kink."""
+    out = []
+    for v, amb in enumerate(ora["ambiguous"]):
+        m = np.asarray(amb, bool)
+        if targets is not None:
+            m = m | (np.abs(ora["images"][v] - targets[v]) < L1_KINK).any(axis=0)
+        out.append(m)
+    return out
 
 
 def excluded_gaussians(ora, n, opts, targets=None):
-    """Gaussians whose gradient may differ legitimately: those listed in a tile
-    that holds an ambiguous pixel or (given the targets) a pixel on the L1
-    kink, those with an ambiguous decision of their own, and those sitting on
-    a kink (colour clamp, Jacobian clamp)."""
+    """Gaussians whose gradient may differ legitimately: those whose FP64 alpha
+    reaches alpha_min / 2 at an ambiguous pixel or (given the targets) at a
+    pixel on the L1 kink, those with an ambiguous decision of their own, and
+    those sitting on a kink of their own (colour clamp, Jacobian clamp)."""
+    rec = oracle.touching(ora, flagged_pixels(ora, targets), opts)
     ex = np.zeros(n, bool)
-    vals = ora["bins"]["values"]
-    ranges = ora["bins"]["ranges"]
-    for v, amb in enumerate(ora["ambiguous"]):
-        if targets is not None:
-            amb = amb.astype(bool) | (np.abs(ora["images"][v] - targets[v]) < L1_KINK).any(axis=0)
-        if not amb.any():
-            continue
-        gx, gy = ora["grids"][v]
-        H, W = amb.shape
-        tw, th = opts.tile_w, opts.tile_h
-        pad = np.zeros((gy * th, gx * tw), bool)
-        pad[:H, :W] = amb
-        tiles = np.nonzero(pad.reshape(gy, th, gx, tw).any(axis=(1, 3)).ravel())[0]
-        for t in tiles:
-            gt = ora["tile_base"][v] + t
-            s, e = ranges[gt]
-            ex[vals[s:e] % n] = True
+    V = len(ora["records"])
+    for v in range(V):
+        ex |= rec[v * n:(v + 1) * n]
     for r in ora["records"]:
-        ex |= r["margin"] < DELTA
+        ex |= record_ambiguous(r)
         ex |= r["grad_margin"] < DELTA
+        ex |= r["color_margin"] < oracle.DELTA_COLOR
     return ex
+
+
+def assert_excluded_fraction(ex, checked, report=None, limit=MAX_EXCLUDED):
+    """The exclusions remove at most `limit` of the checked Gaussians."""
+    checked = np.asarray(checked, bool)
+    frac = float((ex & checked).sum()) / max(int(checked.sum()), 1)
+    if report is not None:
+        report["excluded_fraction"] = frac
+    print(f"excluded {int((ex & checked).sum())} of {int(checked.sum())} checked Gaussians ({100 * frac:.3f} %)",
+          flush=True)
+    assert frac < limit, frac
+    return frac
 
 
 def compare_grads(gpu: dict, ora_grads: np.ndarray, exclude: np.ndarray, tol=GRAD_TOL, report=None):

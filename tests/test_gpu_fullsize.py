@@ -48,6 +48,7 @@ def test_config1_full_step_matches_oracle():
     parity.compare_images(parity.gpu_images(r), ora, rep)
     assert abs(float(loss.item()) - ora["loss"]) <= 1e-5 * ora["loss"]
     ex = parity.excluded_gaussians(ora, s.n, parity.opts_for((8, 32)), s.targets)
+    parity.assert_excluded_fraction(ex, ora["count"] > 0, rep)
     parity.compare_grads(parity.gpu_grad_groups(r.grads), ora["grads"], ex, report=rep)
     keep = ~ex
     S = r.S.cpu().numpy().astype(np.float64)
@@ -101,18 +102,14 @@ def check_sampled_views(s, r, views):
         d = np.sign(fo["images"][0] - s.targets[v]) / (3.0 * W * H * V)
         kink = np.abs(fo["images"][0] - s.targets[v]) < 1e-5
         d_g = np.sign(gimgs[v].astype(np.float64) - s.targets[v]) / (3.0 * W * H * V)
-        assert np.array_equal((d == d_g)[~kink], np.ones((~kink).sum(), bool))
+        amb = fo["ambiguous"][0].astype(bool)[None]
+        assert np.all((d == d_g)[~kink & ~amb])
         bo = oracle.backward(P, [c], opts, fo, [d])
         vis = fo["records"][0]["visible"].astype(bool)
-        ex = parity.excluded_gaussians(fo, n, opts)
-        kinked = np.zeros(n, bool)
-        if kink.any():
-            ys, xs = np.nonzero(kink.any(axis=0))
-            gx = (W + o.tile_w - 1) // o.tile_w
-            for t in np.unique((ys // o.tile_h) * gx + xs // o.tile_w):
-                a, b = fo["bins"]["ranges"][t]
-                kinked[fo["bins"]["values"][a:b] % n] = True
-        sel = vis & ~ex & ~kinked
+        # Gaussians touching an ambiguous pixel or one on the L1 kink
+        ex = parity.excluded_gaussians(fo, n, opts, [s.targets[v]])
+        parity.assert_excluded_fraction(ex, vis, rep)
+        sel = vis & ~ex
         gg = g2d_all[v * n:(v + 1) * n, :9].cpu().numpy().astype(np.float64)[sel]
         go = bo["g2d"].T[sel]
         for k in range(9):
@@ -121,7 +118,7 @@ def check_sampled_views(s, r, views):
             rms = np.sqrt(np.mean(b_ ** 2))
             assert rel <= 1e-3, (v, k, rel)
             assert np.all(np.abs(a_ - b_) <= 1e-3 * (np.abs(b_) + 1e-2 * rms)), (v, k)
-        print("view", v, rep, "grad2d records checked", int(sel.sum()), "kink-excluded", int(kinked.sum()))
+        print("view", v, rep, "grad2d records checked", int(sel.sum()), "excluded", int((vis & ex).sum()))
 
 
 def test_config2_sampled_views_match_oracle(c2):
@@ -156,6 +153,7 @@ def check_subset(s, r):
         del fo, bo
     gpu = parity.gpu_grad_groups({k: v_[..., torch.from_numpy(sub).cuda()] for k, v_ in r.grads.items()})
     rep = {}
+    parity.assert_excluded_fraction(excl, cnt > 0, rep)
     parity.compare_grads(gpu, grads, excl, report=rep)
     Sg = r.S.cpu().numpy().astype(np.float64)[sub]
     rms = np.sqrt(np.mean(S ** 2))
@@ -238,20 +236,14 @@ def test_config4_window_matches_oracle():
     # (their whole footprint is window pixels), under the full frame's dL/dC
     t_img = s.targets[v][:, oy:oy + h, ox:ox + w]
     d = np.sign(fo["images"][0] - t_img) / (3.0 * W * H * V)
-    kink = np.abs(fo["images"][0] - t_img) < parity.L1_KINK
     bo = oracle.backward(P, [wc], wo, fo, [d])
     rec = fo["records"][0]
     gx, gy = fo["grids"][0]
     x0, y0, x1, y1 = rec["rect"]
     inner = rec["visible"].astype(bool) & (x0 >= 1) & (y0 >= 1) & (x1 <= gx - 2) & (y1 <= gy - 2)
-    ex = parity.excluded_gaussians(fo, n, wo)
-    kinked = np.zeros(n, bool)
-    if kink.any():
-        ys, xs = np.nonzero(kink.any(axis=0))
-        for t in np.unique((ys // tile[1]) * gx + xs // tile[0]):
-            a_, b_ = fo["bins"]["ranges"][t]
-            kinked[fo["bins"]["values"][a_:b_] % n] = True
-    sel = np.nonzero(inner & ~ex & ~kinked)[0]
+    ex = parity.excluded_gaussians(fo, n, wo, [t_img])
+    parity.assert_excluded_fraction(ex, inner, rep)
+    sel = np.nonzero(inner & ~ex)[0]
     L = r.layout
     g2d = r.ws_tensor("grad2d", torch.float32, C.GSR_SLOT_FLOATS * L.vn).view(-1, C.GSR_SLOT_FLOATS)
     gg = g2d[v * n + torch.from_numpy(sel).cuda(), :9].cpu().numpy().astype(np.float64)
