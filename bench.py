@@ -10,10 +10,13 @@ stored in Morton order of their means (the layout the framework keeps; the
 generator's random order is timed too, for reference).
 
 Prints one JSON line: Mpixels/s of the batched step (value), Gaussians/s,
-the plain per-view rate and the ratio, the roofline of the dominant kernel
-(timed with device events on its stream over a second pass of eager steps),
-a sampled parity check of the timed outputs against the FP64 oracle, and the
-oracle's own rate on the host cores.
+the plain per-view rate and the ratio, the spread of single steps, device
+memory, the roofline of the dominant kernel (the fused raster: algorithmic
+HBM bytes over its time from device events on its stream over a second pass
+of eager steps, the whole step's algorithmic bytes over the step time, and
+the blended pairs' float operations), the timed outputs' parity against the
+FP64 oracle on every view the oracle renders, and the oracle's own rate on
+the host cores.
 """
 import argparse
 import json
@@ -28,8 +31,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
-# Algorithmic float operations per evaluated (pixel, Gaussian) pair, counted
-# from the method (not from the instructions): forward offset (2), quadratic
+# Algorithmic float operations per blended (pixel, Gaussian) pair (alpha at
+# least alpha_min, before the stop), counted from the method (not from the
+# instructions): forward offset (2), quadratic
 # form (6), exponent and opacity (2), threshold tests (2), transmittance
 # update (2), colour accumulation (7) = 21; reverse pass: the same alpha (12),
 # transmittance recovery (2), dL/dalpha over 3 channels (12), colour and
@@ -64,6 +68,49 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def b_alg_batched(n, U, K, F, vis, isect, pixels):
+    """Algorithmic HBM bytes of one batched step (every view in one pass):
+    geometry (means, log-scales, quaternions: 40 B) of every Gaussian once,
+    opacity and SH (4 + 4K) of every Gaussian visible in some view once,
+    per visible (view, Gaussian) 152 B (48 B record written, 32 B of scan and
+    scatter, 36 B 2D gradient written and read back, 36 B of the reverse
+    projection's per-view reads), per intersection 140 B (8 B key emitted, a
+    two-pass sort at 2 x 24 B, a 40 B record gather forward and another
+    backward), per pixel 52 B (colour, T and last written: 20 B; target,
+    colour, T and last read: 32 B), and the gradients (read-modify-write of
+    4F B) plus 16 B of densification statistics of every Gaussian visible in
+    some view."""
+    return 40 * n + (4 + 4 * K) * U + 152 * vis + 140 * isect + 52 * pixels + (2 * 4 * F + 16) * U
+
+
+def b_alg_plain(n, K, F, n_views, vis, isect, pixels):
+    """The same step as one pass per view: every view reads the means for its
+    cull (12 B per Gaussian) and its visible Gaussians' parameters again;
+    per visible (view, Gaussian) c_V = 200 + 4K + 12F bytes (the batched
+    per-pair traffic plus that view's parameter reads and gradient
+    read-modify-write)."""
+    c_v = 200 + 4 * K + 12 * F
+    return 12 * n * n_views + c_v * vis + 140 * isect + 52 * pixels
+
+
+def b_alg_fused(vis, isect, pixels):
+    """Algorithmic HBM bytes of the fused raster kernel (forward, L1 and
+    reverse pass of every tile): a 40 B record gather per intersection in
+    each direction, 52 B per pixel (image, T, last out; target in), and the
+    36 B 2D gradient of every visible record written once."""
+    return 80 * isect + 52 * pixels + 36 * vis
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +133,9 @@ def main():
     ap.add_argument("--order", choices=["morton", "random"], default="morton",
                     help="storage order of the Gaussians: Morton order of their means (the layout the framework "
                          "keeps), or the generator's random order")
+    ap.add_argument("--oracle-configs", default="",
+                    help="comma-separated configs whose whole FP64 oracle step (0, 1) or one view of it (3, 4) "
+                         "is also timed on the host cores")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (a kernel of known traffic, to scale "
                          "hardware byte counters)")
@@ -127,6 +177,10 @@ def main():
         torch.cuda.synchronize()
         del a, b
     tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else (16, 16)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    scene_bytes = sum(t.numel() * t.element_size() for t in params.values()) + cams.numel() * 4 + targets.numel() * 4
+    torch.cuda.reset_peak_memory_stats()
     rb = Rasterizer(scene.n, scene.sh_degree, sizes, mode="batched", tile=tile, profile_stages=1,
                     lds_batch=args.lds_batch, grid_per_cu=args.grid_per_cu, bwd_reduce=args.bwd_reduce)
     rb.step_l1(params, cams, targets, stats=True)
@@ -157,17 +211,31 @@ def main():
     wall = time.perf_counter() - w0
     ms_batched = e0.elapsed_time(e1) / args.steps
     log(f"batched graph step {ms_batched:.3f} ms (wall {1000 * wall / args.steps:.3f} ms)")
+    # the spread of single steps: each replay timed alone (after the timed region)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in evs:
+        a.record(stream)
+        rb.launch(stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    single = np.array([a.elapsed_time(b) for a, b in evs])
+    spread = {"median": round(float(np.median(single)), 4), "p10": round(float(np.percentile(single, 10)), 4),
+              "p90": round(float(np.percentile(single, 90)), 4)}
+    log(f"single steps: {spread}")
+    free1 = torch.cuda.mem_get_info()[0]
+    memory = {"workspace_bytes": int(rb.ws_bytes), "scene_bytes": int(scene_bytes),
+              "torch_peak_allocated_bytes": int(torch.cuda.max_memory_allocated()),
+              "device_bytes_taken_by_rasterizer": int(free0 - free1)}
+    log(f"memory: {memory}")
     counts = rb.counts()
     images_gpu = rb.images.cpu().numpy()
-    # the smallest view's 2D gradients of the timed step, for the parity check (later
-    # stages reuse the workspace)
-    v_small = int(np.argmin([w * h for w, h in sizes]))
+    # the timed step's 2D gradients of every view, for the parity check (later stages
+    # reuse the workspace)
     S_ = C.GSR_SLOT_FLOATS
-    g2d_small = rb.ws_tensor("grad2d", torch.float32, S_ * rb.layout.vn).view(-1, S_)[
-        v_small * scene.n:(v_small + 1) * scene.n, :9].cpu().numpy().astype(np.float64)
+    g2d_all = rb.ws_tensor("grad2d", torch.float32, S_ * rb.layout.vn).view(-1, S_)[:, :9].cpu().numpy()
     loss_gpu = float(rb.loss.item())
     last = rb.ws_tensor("pix_last", torch.int32, rb.pixels).cpu().numpy().astype(np.int64)
-    pairs = int(last.sum())
+    walked = int(last.sum())
 
     # ---- per-kernel device time: the same step eagerly, stage events on its stream
     stage_tot = {}
@@ -182,6 +250,14 @@ def main():
     stage_ms = {k: v[0] / args.steps for k, v in stage_tot.items()}
     log("stages (ms/step): " + ", ".join(f"{k} {v:.3f}" for k, v in sorted(stage_ms.items(), key=lambda x: -x[1])))
     dom = max(stage_ms, key=stage_ms.get)
+    # profiling-only forward: pairs blended (alpha >= alpha_min before the stop) and pairs the
+    # lanes evaluated after the sub-block culling
+    pc_img = torch.empty_like(rb.images)
+    bl, ev = rb.pair_counts(params, cams, images=pc_img, stream=stream)
+    torch.cuda.synchronize()
+    blended, evaluated = int(bl.to(torch.int64).sum().item()), int(ev.to(torch.int64).sum().item())
+    del pc_img, bl, ev
+    log(f"pairs: walked {walked}, evaluated {evaluated}, blended {blended}")
 
     # ---- plain per-view launches
     ms_plain = None
@@ -372,46 +448,58 @@ def main():
             log(f"partition: {fcs['partition']}")
             del pts, pts_host
 
-    # ---- algorithmic work of the dominant kernel
+    # ---- roofline: algorithmic bytes (and blended-pair flops) against the measured times
     n, V = scene.n, scene.n_views
     P = scene.pixels
     I = counts.intersections_total
     vis = counts.visible_total
+    U = counts.visible_union
     K = 3 * (scene.sh_degree + 1) ** 2
-    roof = None
-    if dom == "fused raster":
-        flops = pairs * (FLOPS_FWD_PAIR + FLOPS_BWD_PAIR)
-        achieved = flops / (stage_ms[dom] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": fused_traffic(opt) if args.config == 2 else None, "kernel": "k_fused",
-                "pairs": pairs, "flops_per_pair": FLOPS_FWD_PAIR + FLOPS_BWD_PAIR}
-    else:
-        # per-Gaussian streams (project / project_bwd / emit / sort) are bound by HBM
-        bytes_by_stage = {
-            "project": 44 * n + (4 * K + 64 + 48) * vis,
-            "project_bwd": 4 * n + (4 * (11 + K)) * n * 2 + 48 * vis,
-            "emit": 4 * n + 20 * vis + 8 * I,
-            "sort": 16 * I,
-        }
-        b = bytes_by_stage.get(dom, 0)
-        achieved = b / (stage_ms[dom] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom}
+    F = 11 + K
+    t_fused = stage_ms.get("fused raster")
+    b_step = b_alg_batched(n, U, K, F, vis, I, P)
+    b_fused = b_alg_fused(vis, I, P)
+    gbs_step = b_step / (ms_batched * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": "k_fused", "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    if t_fused:
+        gbs_fused = b_fused / (t_fused * 1e-3) / 1e9
+        roof.update(achieved=round(gbs_fused, 1), frac=round(gbs_fused / HBM_PEAK_GBS, 4), bytes_alg=int(b_fused),
+                    ms=round(t_fused, 4))
+        flops = blended * (FLOPS_FWD_PAIR + FLOPS_BWD_PAIR)
+        tf = flops / (t_fused * 1e-3) / 1e12
+        roof["alu"] = {"blended_pairs": blended, "evaluated_pairs": evaluated, "walked_pairs": walked,
+                       "flops_per_blended_pair": FLOPS_FWD_PAIR + FLOPS_BWD_PAIR, "achieved": round(tf, 3),
+                       "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4)}
+    roof["traffic"] = fused_traffic(opt) if args.config == 2 else None
+    roof["step"] = {"bytes_alg": int(b_step), "ms": round(ms_batched, 4), "achieved": round(gbs_step, 1),
+                    "frac": round(gbs_step / HBM_PEAK_GBS, 4)}
+    if ms_plain:
+        b_plain = b_alg_plain(n, K, F, V, vis, I, P)
+        g = b_plain / (ms_plain * 1e-3) / 1e9
+        roof["plain_step"] = {"bytes_alg": int(b_plain), "ms": round(ms_plain, 3), "achieved": round(g, 1),
+                              "frac": round(g / HBM_PEAK_GBS, 4)}
     roof["stage_ms"] = {k: round(v, 4) for k, v in stage_ms.items()}
+    log(f"roofline: {roof}")
 
-    # ---- sampled parity of the timed outputs + the oracle's own rate
+    # ---- parity of the timed outputs on every view the oracle renders, and the oracle's own rate
     parity = None
     cpu = None
     if not (args.no_parity and args.no_cpu):
         import oracle
-        order = [int(i) for i in np.argsort([w * h for w, h in sizes], kind="stable")]
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         Pn = oracle.Params.from_scene(scene)
         o = oracle.default_opts(tile_w=opt.tile_w, tile_h=opt.tile_h)
-        done, t_ora = [], 0.0
+        # views taken round-robin over the resolutions, so the sample mixes sizes like the batch
+        groups = {}
+        for v, wh in enumerate(sizes):
+            groups.setdefault(wh, []).append(v)
+        order = []
+        while any(groups.values()):
+            for wh in sorted(groups, key=lambda x: -x[0] * x[1]):
+                if groups[wh]:
+                    order.append(groups[wh].pop(0))
+        done, t_ora, checks = [], 0.0, []
         for v in order:
-            # the oracle on the host cores: views smallest first until about ten seconds of work
             c = scene.cameras[v]
             W, H = c["W"], c["H"]
             t1 = time.time()
@@ -421,31 +509,76 @@ def main():
             bo = oracle.backward(Pn, [c], o, fo, [d])
             t_ora += time.time() - t1
             done.append(v)
-            if parity is None and not args.no_parity:
+            if not args.no_parity:
                 off = 3 * sum(w * h for w, h in sizes[:v])
                 img_g = images_gpu[off:off + 3 * W * H].reshape(3, H, W).astype(np.float64)
                 amb = fo["ambiguous"][0].astype(bool)
                 err = np.abs(img_g - img_o) / np.maximum(1.0, np.abs(img_o))
                 rel_l2 = float(np.linalg.norm(img_g - img_o) / np.linalg.norm(img_o))
-                assert v == v_small
-                g2d = g2d_small
-                go = bo["g2d"].T
+                # 2D gradients of the view's records, leaving out those whose alpha reaches
+                # alpha_min / 2 at an ambiguous pixel or at a pixel on the L1 kink
+                kink = (np.abs(img_o - scene.targets[v]) < 1e-5).any(axis=0)
                 visv = fo["records"][0]["visible"].astype(bool)
-                g_rel = float(np.linalg.norm(g2d[visv] - go[visv]) / np.linalg.norm(go[visv]))
-                parity = {"view": v, "size": [W, H], "image_max_rel": float(err[:, ~amb].max()),
-                          "image_rel_l2": rel_l2, "ambiguous_pixels": int(amb.sum()),
-                          "grad2d_rel_l2": g_rel,
-                          "pass": bool(err[:, ~amb].max() <= 1e-5 and rel_l2 <= 1e-5 and g_rel <= 1e-3)}
-                log(f"parity view {v}: {parity}")
+                ex = oracle.touching(fo, [amb | kink], o)[:n] | (fo["records"][0]["margin"] < oracle.DELTA_GAUSS)
+                sel = visv & ~ex
+                g2d = g2d_all[v * n:(v + 1) * n][sel].astype(np.float64)
+                go = bo["g2d"].T[sel]
+                g_rel = float(np.linalg.norm(g2d - go) / np.linalg.norm(go))
+                rms = np.sqrt(np.mean(go * go, axis=0))
+                g_elem = float(np.max(np.abs(g2d - go) - 1e-3 * (np.abs(go) + 1e-2 * rms)))
+                checks.append({"view": v, "image_max_rel": float(err[:, ~amb].max()), "image_rel_l2": rel_l2,
+                               "ambiguous_pixels": int(amb.sum()), "grad2d_rel_l2": g_rel,
+                               "grad2d_elem_excess": g_elem,
+                               "excluded_fraction": float((ex & visv).sum() / max(visv.sum(), 1))})
+                log(f"parity view {v}: {checks[-1]}")
             del fo, bo
-            if args.no_cpu or t_ora >= 10.0:
+            if t_ora >= 10.0:
                 break
+        if checks:
+            ok = all(c_["image_max_rel"] <= 1e-5 and c_["image_rel_l2"] <= 1e-5 and c_["grad2d_rel_l2"] <= 1e-3
+                     and c_["grad2d_elem_excess"] <= 0.0 and c_["excluded_fraction"] < 0.05 for c_ in checks)
+            parity = {"views": [c_["view"] for c_ in checks],
+                      "image_max_rel": max(c_["image_max_rel"] for c_ in checks),
+                      "image_rel_l2": max(c_["image_rel_l2"] for c_ in checks),
+                      "grad2d_rel_l2": max(c_["grad2d_rel_l2"] for c_ in checks),
+                      "grad2d_elem_excess": max(c_["grad2d_elem_excess"] for c_ in checks),
+                      "ambiguous_pixels": sum(c_["ambiguous_pixels"] for c_ in checks),
+                      "pixels": sum(sizes[c_["view"]][0] * sizes[c_["view"]][1] for c_ in checks),
+                      "excluded_fraction_max": max(c_["excluded_fraction"] for c_ in checks),
+                      "pass": bool(ok)}
+            log(f"parity: {parity}")
         if not args.no_cpu:
             px = sum(sizes[v][0] * sizes[v][1] for v in done)
             cpu = {"value": round(px / t_ora / 1e6, 5), "unit": "Mpixels/s", "cores": threads, "kind": "oracle",
+                   "cpu": cpu_model(),
                    "sample": f"FP64 oracle forward + L1 + backward (projection of all {n} Gaussians per view) "
-                             f"of {len(done)} of the {V} views, smallest first ({px} pixels), {t_ora:.1f} s"}
+                             f"of {len(done)} of the {V} views, taken round-robin over the resolutions "
+                             f"({px} pixels), {t_ora:.1f} s"}
             log(f"cpu baseline: {cpu}")
+
+    # ---- the oracle on the other configurations (whole steps of the small ones, one view of the large)
+    oracle_cfg = None
+    if args.oracle_configs:
+        import oracle
+        oracle_cfg = {}
+        for k in [int(x) for x in args.oracle_configs.split(",") if x]:
+            sc = scenes.make_config(k)
+            Pk = oracle.Params.from_scene(sc)
+            ok_ = oracle.default_opts()
+            views = list(range(sc.n_views)) if k in (0, 1) else [0]
+            t1 = time.time()
+            for v in views:
+                c = sc.cameras[v]
+                fo = oracle.forward(Pk, [c], ok_)
+                d = np.sign(fo["images"][0] - sc.targets[v]) / (3.0 * c["W"] * c["H"] * sc.n_views)
+                oracle.backward(Pk, [c], ok_, fo, [d])
+                del fo
+            dt = time.time() - t1
+            px = sum(sc.cameras[v]["W"] * sc.cameras[v]["H"] for v in views)
+            oracle_cfg[sc.name] = {"views": len(views), "of_views": sc.n_views, "s": round(dt, 2),
+                                   "mpixels_per_s": round(px / dt / 1e6, 4)}
+            log(f"oracle {sc.name}: {oracle_cfg[sc.name]}")
+            del sc, Pk
 
     mpix = P / (ms_batched * 1e-3) / 1e6
     out = {
@@ -473,14 +606,18 @@ def main():
         "plain_mpixels_per_s": None if ms_plain is None else round(P / (ms_plain * 1e-3) / 1e6, 2),
         "batched_vs_plain": None if ms_plain is None else round(ms_plain / ms_batched, 3),
         "random_order_ms_per_step": None if ms_random is None else round(ms_random, 4),
+        "step_ms_single": spread,
+        "memory": memory,
         "loss": loss_gpu,
-        "counts": {"visible": vis, "union": counts.visible_union, "intersections": I, "pairs": pairs},
+        "counts": {"visible": vis, "union": counts.visible_union, "intersections": I, "walked_pairs": walked,
+                   "evaluated_pairs": evaluated, "blended_pairs": blended},
         "roofline": roof,
         "adam": adam,
         "fcs": fcs,
         "densify": dens,
         "parity": parity,
         "cpu_baseline": cpu,
+        "oracle_other_configs": oracle_cfg,
     }
     print(json.dumps(out), flush=True)
 

@@ -69,7 +69,10 @@ typedef int32_t gsr_status;
 #define GSR_MODE_PLAIN 0   /* one launch chain per view, per-view count read-back */
 #define GSR_MODE_BATCHED 1 /* all views in one chain, persistent fused raster, capturable */
 
-/* Reverse-compositing form (Sec. "(3) differentiation"). */
+/* Reverse pass of the blending sum (Sec. 3.2): how the transmittance in front
+ * of each entry is obtained while walking a pixel's list back to front.  The
+ * paper fixes only the sum; both forms give the same gradients (the choice
+ * is a memory / time trade-off of this implementation). */
 #define GSR_BWD_AUTO 0      /* stored history if it fits history_budget_bytes, else recompute */
 #define GSR_BWD_RECOMPUTE 1 /* recover T_i = T_{i+1} / (1 - alpha_i) walking back */
 #define GSR_BWD_STORED 2    /* read the per-(entry, pixel) transmittance saved by the forward */
@@ -197,15 +200,23 @@ gsr_status gsr_forward(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera 
                        void *stream);
 
 /* Reverse pass for an arbitrary image gradient dL_dimages (packed like
- * images) after gsr_forward on the same plan and workspace.  Writes grads
- * (or adds, with accumulate_grads) and accumulates stats (may be NULL). */
+ * images) after gsr_forward on the same plan and workspace: the exact
+ * derivative of the blending sum (Sec. 3.2) through the projection to every
+ * raw parameter, and the view-space gradient statistic and visible count
+ * that selective densification reads (Sec. 3.3).  Writes grads (or adds,
+ * with accumulate_grads) and accumulates stats (may be NULL).
+ * GSR_ERR_STATE when no gsr_forward precedes it on this plan (each forward
+ * allows one reverse pass). */
 gsr_status gsr_backward(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams,
                         const float *dL_dimages, const gsr_grads *grads, const gsr_stats *stats,
                         void *ws, size_t ws_bytes, void *stream);
 
-/* One fused training step: forward, L = mean over views of the per-view mean
- * |image - target|, reverse pass (dL/dimage = sign(image - target) /
- * (3 H W n_views), sign(0) = 0), statistics.  loss: one device float. */
+/* One fused training step of a block (Sec. 3, per-block fine training; its
+ * image loss is the L1 term of vanilla 3DGS, App. A.1): forward, L = mean over
+ * views of the per-view mean |image - target|, reverse pass (dL/dimage =
+ * sign(image - target) / (3 H W n_views), sign(0) = 0), statistics (Sec. 3.3).
+ * loss: one device float.  Inputs, outputs and errors as gsr_forward and
+ * gsr_backward. */
 gsr_status gsr_forward_backward_l1(gsr_plan *plan, const gsr_gaussians *g,
                                    const gsr_camera *cams, const float *targets, float *images,
                                    float *loss, const gsr_grads *grads, const gsr_stats *stats,
@@ -219,8 +230,10 @@ gsr_status gsr_visibility_mask(gsr_plan *plan, const gsr_gaussians *g, const gsr
                                const float *aabb, uint32_t *view_bits, uint8_t *keep_out,
                                uint8_t *in_block, void *ws, size_t ws_bytes, void *stream);
 
-/* Records the batched fused step (same arguments as gsr_forward_backward_l1)
- * into a graph owned by the plan; gsr_graph_launch replays it on a stream.
+/* Graph form of the training step (Sec. 3: each block trains on its
+ * assigned cameras, all of them per step here).  Records the batched fused
+ * step (same arguments as gsr_forward_backward_l1) into a graph owned by the
+ * plan; gsr_graph_launch replays it on a stream.
  * The stream must be capturable (not the legacy null stream).  Requires
  * GSR_MODE_BATCHED.  Replays read the same buffers, so new parameters or
  * poses are taken by writing into them. */
@@ -292,6 +305,17 @@ gsr_status gsr_plan_set_tuning(gsr_plan *plan, const gsr_options *opt);
 
 gsr_status gsr_render_depth(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams, float *images,
                             float *depth, void *ws, size_t ws_bytes, void *stream);
+
+/* Profiling: the forward render of gsr_forward (same images) that also
+ * counts, per pixel, the (pixel, list entry) pairs of the blending sum
+ * (Sec. 3.2): counts[p] = pairs blended into pixel p (alpha >= alpha_min
+ * before the stop), counts[P + p] = pairs whose alpha the pixel's lane
+ * evaluated after the per-sub-block culling (P = sum_v H_v W_v, pixels packed
+ * by view in input order, row-major).  counts: device [2 P] u32, written.
+ * The reverse pass cannot follow this call (GSR_ERR_STATE until the next
+ * gsr_forward).  Errors as gsr_forward. */
+gsr_status gsr_pair_counts(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams, float *images,
+                           uint32_t *counts, void *ws, size_t ws_bytes, void *stream);
 
 gsr_status gsr_camera_coverage(gsr_plan *plan, const gsr_camera *cams, const float *depth, const float *blocks,
                                int32_t n_blocks, float tau, uint32_t *counts, float *ratio, uint8_t *selected,

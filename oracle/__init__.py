@@ -40,6 +40,11 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
+        other = os.environ.get("GSR_ORACLE_LIBRARY")  # another build of this oracle (sanitizer runs)
+        if other:
+            _lib = ctypes.CDLL(other)
+            _declare(_lib)
+            return _lib
         if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
             build(force=True)
         _lib = ctypes.CDLL(_LIB_PATH)
@@ -115,7 +120,7 @@ def _declare(L):
                           ctypes.c_int64, _i64, _u32, _i64, _i64]
     L.ora_render.argtypes = [_O, ctypes.c_int32, ctypes.c_int32, _i64, _i64, ctypes.c_int64,
                              _d, _d, _d, _d, _d, _u8, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                             _d, _d, _i32, _d, _u8, _i64]
+                             _d, _d, _i32, _d, _u8, _i64, _i32]
     L.ora_render_brute.argtypes = [_O, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _i32, _i32,
                                    _u32, _i64, _d, _d, _d, _d, _d, _d, _d, _i32]
     L.ora_render_bwd.argtypes = [_O, ctypes.c_int32, ctypes.c_int32, _i64, _i64, ctypes.c_int64,
@@ -277,7 +282,7 @@ def forward(P: Params, cams: list, opts: Opts, keep=None, delta=DELTA_GAUSS, del
     rec_amb = np.ascontiguousarray((R["margin"] < delta).astype(np.uint8)
                                    | (2 * (R["depth_margin"] < delta_depth_round)).astype(np.uint8))
     nr = n * V
-    images, Tf, last, D, amb, sigs = [], [], [], [], [], []
+    images, Tf, last, D, amb, sigs, blended = [], [], [], [], [], [], []
     L = lib()
     for v, c in enumerate(cams):
         W, H = c["W"], c["H"]
@@ -287,12 +292,13 @@ def forward(P: Params, cams: list, opts: Opts, keep=None, delta=DELTA_GAUSS, del
         d = np.zeros((H, W))
         a = np.zeros((H, W), np.uint8)
         sg = np.zeros((H, W), np.int64)
+        nb = np.zeros((H, W), np.int32)
         rv = np.ascontiguousarray(bins["ranges"][tile_base_v[v]:tile_base_v[v] + tiles_per_view[v]])
         L.ora_render(ctypes.byref(opts), W, H, _p(rv, _i64), _p(bins["values"], _i64), nr,
                      _p(R["mean2d"], _d), _p(R["conic"], _d), _p(R["opacity"], _d),
                      _p(R["color"], _d), _p(R["depth"], _d), _p(rec_amb, _u8), delta_alpha, delta_T,
                      delta_depth_gap,
-                     _p(img, _d), _p(t, _d), _p(la, _i32), _p(d, _d), _p(a, _u8), _p(sg, _i64))
+                     _p(img, _d), _p(t, _d), _p(la, _i32), _p(d, _d), _p(a, _u8), _p(sg, _i64), _p(nb, _i32))
         # A Gaussian whose own decisions are ambiguous may be listed in one
         # more tile row or column by another implementation: mark the pixels
         # of that enlarged area where it could contribute (alpha above half
@@ -318,12 +324,13 @@ def forward(P: Params, cams: list, opts: Opts, keep=None, delta=DELTA_GAUSS, del
                 a[ys, xs] = 1
         images.append(img)
         sigs.append(sg)
+        blended.append(nb)
         Tf.append(t)
         last.append(la)
         D.append(d)
         amb.append(a)
     return dict(records=recs, R=R, bins=bins, images=images, T_final=Tf, last=last, depth=D,
-                ambiguous=amb, signature=sigs, tile_base=tile_base_v, tiles_per_view=tiles_per_view, grids=grids,
+                ambiguous=amb, signature=sigs, blended=blended, tile_base=tile_base_v, tiles_per_view=tiles_per_view, grids=grids,
                 depth_bits=depth_bits)
 
 

@@ -399,8 +399,9 @@ typedef struct {
 static int composite_pixel(const ora_opts *o, const ora_records *rc, const int64_t *vals,
                            int64_t len, double px, double py, double delta, double delta_T,
                            double delta_depth, double C[3], double *D, double *Tout, int *amb,
-                           double *alpha_hist, double *T_hist, int64_t *sig) {
+                           double *alpha_hist, double *T_hist, int64_t *sig, int *n_blended) {
   double T = 1.0;
+  int nb = 0; /* entries blended (alpha >= alpha_min before the stop) */
   double prev_depth = NAN; /* depth of the last entry that may blend into this pixel */
   int64_t prev_r = -1;
   C[0] = C[1] = C[2] = 0;
@@ -440,8 +441,10 @@ static int composite_pixel(const ora_opts *o, const ora_records *rc, const int64
     if (alpha_hist) { alpha_hist[j] = alpha; T_hist[j] = T; }
     h = h * 1000003u + (uint64_t)(r + 1) * (uint64_t)(j + 1);
     T = Tn;
+    nb++;
   }
   *Tout = T;
+  if (n_blended) *n_blended = nb;
   if (sig) *sig = (int64_t)(h ^ (uint64_t)j);
   return (int)j;
 }
@@ -452,8 +455,8 @@ void ora_render(const ora_opts *o, int32_t W, int32_t H, const int64_t *ranges_v
                 const int64_t *values, int64_t nr, const double *mean2d, const double *conic,
                 const double *opacity, const double *color, const double *depth,
                 const uint8_t *rec_amb, double delta, double delta_T, double delta_depth, double *image,
-                double *T_final,
-                int32_t *last, double *depth_out, uint8_t *ambiguous, int64_t *signature) {
+                double *T_final, int32_t *last, double *depth_out, uint8_t *ambiguous, int64_t *signature,
+                int32_t *blended) {
   ora_records rc = {nr, mean2d, conic, opacity, color, depth, rec_amb};
   int tiles_x = (W + o->tile_w - 1) / o->tile_w;
   int64_t P = (int64_t)W * H;
@@ -465,8 +468,10 @@ void ora_render(const ora_opts *o, int32_t W, int32_t H, const int64_t *ranges_v
     double C[3], D, T;
     int amb;
     int64_t sg;
+    int nb;
     int n = composite_pixel(o, &rc, values + s, e - s, px, py, delta, delta_T, delta_depth, C, &D, &T, &amb, NULL,
-                            NULL, &sg);
+                            NULL, &sg, &nb);
+    if (blended) blended[pix] = nb;
     for (int ch = 0; ch < 3; ch++) image[ch * P + pix] = C[ch] + T * o->bg[ch];
     T_final[pix] = T;
     last[pix] = n;
@@ -513,7 +518,7 @@ void ora_render_brute(const ora_opts *o, int32_t W, int32_t H, int64_t nr, const
     for (int64_t k = 0; k < m; k++) vals[k] = list[k].rec;
     double C[3], D, T;
     int amb;
-    int n = composite_pixel(o, &rc, vals, m, px, py, 0.0, 0.0, 0.0, C, &D, &T, &amb, NULL, NULL, NULL);
+    int n = composite_pixel(o, &rc, vals, m, px, py, 0.0, 0.0, 0.0, C, &D, &T, &amb, NULL, NULL, NULL, NULL);
     for (int ch = 0; ch < 3; ch++) image[ch * P + pix] = C[ch] + T * o->bg[ch];
     T_final[pix] = T;
     last[pix] = n;
@@ -550,7 +555,7 @@ void ora_render_bwd(const ora_opts *o, int32_t W, int32_t H, const int64_t *rang
     double *ah = malloc(sizeof(double) * len), *th = malloc(sizeof(double) * len);
     double C[3], D, T;
     int amb;
-    int n = composite_pixel(o, &rc, values + s, len, px, py, 0.0, 0.0, 0.0, C, &D, &T, &amb, ah, th, NULL);
+    int n = composite_pixel(o, &rc, values + s, len, px, py, 0.0, 0.0, 0.0, C, &D, &T, &amb, ah, th, NULL, NULL);
     double g[3] = {dL_dimg[pix], dL_dimg[P + pix], dL_dimg[2 * P + pix]};
     double Bacc[3] = {T * o->bg[0], T * o->bg[1], T * o->bg[2]};
     for (int j = n - 1; j >= 0; j--) {

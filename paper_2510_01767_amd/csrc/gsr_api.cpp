@@ -326,7 +326,8 @@ gsr_status zero_grads(gsr_plan *plan, const gsr_grads *g, void *stream) {
 // read-back of each view's intersection count (the plain form's only sync).
 // Batched: one chain for all views, no host synchronisation.
 gsr_status enqueue_front(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams, const KWs &ws,
-                         void *stream, bool plain_raster_fwd, float *images, float *depth = nullptr) {
+                         void *stream, bool plain_raster_fwd, float *images, float *depth = nullptr,
+                         uint32_t *pair_counts = nullptr) {
   const ViewTable tbl = view_table(*plan);
   const KParams kp = kparams(*plan, g);
   const KOpts ko = kopts(*plan);
@@ -355,7 +356,7 @@ gsr_status enqueue_front(gsr_plan *plan, const gsr_gaussians *g, const gsr_camer
     STAGE(launch_sort(ws, vi.tile_base, nt, stream), "sort");
     if (plain_raster_fwd)
       STAGE(launch_raster_fwd(ws, ko, vi.tile_base, nt, images, V, use_history(*plan) ? 1 : 0, plan->opt.lds_batch,
-                              depth, stream),
+                              depth, pair_counts, stream),
              "raster_fwd");
     base += iv;
   }
@@ -407,7 +408,8 @@ gsr_status enqueue_plain_l1(gsr_plan *plan, const gsr_gaussians *g, const gsr_ca
       return fail(plan, GSR_ERR_CAPACITY, "intersection capacity exceeded in view " + std::to_string(v));
     STAGE(launch_emit(ws, plan->prob.n, V, v, stream), "emit");
     STAGE(launch_sort(ws, vi.tile_base, nt, stream), "sort");
-    STAGE(launch_raster_fwd(ws, ko, vi.tile_base, nt, images, V, hist, plan->opt.lds_batch, nullptr, stream),
+    STAGE(launch_raster_fwd(ws, ko, vi.tile_base, nt, images, V, hist, plan->opt.lds_batch, nullptr, nullptr,
+                            stream),
           "raster_fwd");
     STAGE(launch_l1(ws, ko, vi.tile_base, nt, images, targets, V, stream), "l1");
     STAGE(launch_raster_bwd(ws, ko, vi.tile_base, nt, ws.pix_dLdC, V, hist, plan->opt.lds_batch,
@@ -546,7 +548,7 @@ gsr_status gsr_plan_set_tuning(gsr_plan *plan, const gsr_options *t) {
 
 static gsr_status forward_impl(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams, float *images,
                                float *depth, float *T_final, uint32_t *last, void *ws, size_t ws_bytes,
-                               void *stream) {
+                               void *stream, uint32_t *pair_counts = nullptr) {
   if (!plan) return GSR_ERR_INVALID_ARG;
   if (check_gaussians(g) != GSR_OK || !cams || !images) return fail(plan, GSR_ERR_INVALID_ARG, "null argument");
   gsr_status s = check_ws(plan, ws, ws_bytes);
@@ -555,13 +557,13 @@ static gsr_status forward_impl(gsr_plan *plan, const gsr_gaussians *g, const gsr
   plan->forward_ready = false;
   stage_reset(plan);
   if (plan->opt.mode == GSR_MODE_PLAIN) {
-    s = enqueue_front(plan, g, cams, k, stream, true, images, depth);
+    s = enqueue_front(plan, g, cams, k, stream, true, images, depth, pair_counts);
     if (s != GSR_OK) return s;
   } else {
     s = enqueue_front(plan, g, cams, k, stream, false, nullptr);
     if (s != GSR_OK) return s;
     STAGE(launch_raster_fwd(k, kopts(*plan), 0, k.tiles_total, images, plan->prob.n_views, use_history(*plan) ? 1 : 0,
-                             plan->opt.lds_batch, depth, stream),
+                             plan->opt.lds_batch, depth, pair_counts, stream),
            "raster_fwd");
   }
   if (T_final || last) STAGE(launch_copy_pixels(k, T_final, last, stream), "copy");
@@ -578,6 +580,15 @@ gsr_status gsr_render_depth(gsr_plan *plan, const gsr_gaussians *g, const gsr_ca
                             float *depth, void *ws, size_t ws_bytes, void *stream) {
   if (!depth) return plan ? fail(plan, GSR_ERR_INVALID_ARG, "null argument") : GSR_ERR_INVALID_ARG;
   return forward_impl(plan, g, cams, images, depth, nullptr, nullptr, ws, ws_bytes, stream);
+}
+
+gsr_status gsr_pair_counts(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams, float *images,
+                           uint32_t *counts, void *ws, size_t ws_bytes, void *stream) {
+  if (!counts) return plan ? fail(plan, GSR_ERR_INVALID_ARG, "null argument") : GSR_ERR_INVALID_ARG;
+  gsr_status s = forward_impl(plan, g, cams, images, nullptr, nullptr, nullptr, ws, ws_bytes, stream, counts);
+  // the stored history (if any) was not written: no reverse pass may follow
+  if (plan) plan->forward_ready = false;
+  return s;
 }
 
 gsr_status gsr_back_project(gsr_plan *plan, const gsr_camera *cams, const float *depth, float *points,

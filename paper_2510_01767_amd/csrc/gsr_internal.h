@@ -116,7 +116,8 @@ int launch_scan(const KWs &ws, int64_t tile_lo, int64_t tile_hi, int64_t base, i
 int launch_emit(const KWs &ws, int64_t n, int n_views, int view_only, void *stream);
 int launch_sort(const KWs &ws, int64_t tile_lo, int64_t tile_count, void *stream);
 int launch_raster_fwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, float *images,
-                      int n_views, int store_history, int lds_batch, float *depth, void *stream);
+                      int n_views, int store_history, int lds_batch, float *depth, uint32_t *pair_counts,
+                      void *stream);
 int launch_l1(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *images,
               const float *targets, int n_views, void *stream);
 int launch_raster_bwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, const float *dLdC,

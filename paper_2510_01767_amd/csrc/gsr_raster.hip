@@ -188,12 +188,15 @@ struct Resident {
 // start at c.start + k B; the last one loaded stays resident (`res`).  The
 // pair update is branch-free: a skipped pair adds 0 * colour and keeps T.
 // With DEPTH it also composites the records' depths, D = sum d alpha T
-// (the depth form of the blending sum, Sec. 3.2), from s_depth.
-template <int B, bool HIST, bool DEPTH = false>
+// (the depth form of the blending sum, Sec. 3.2), from s_depth.  With COUNT
+// (profiling) it counts the pairs this lane evaluates after the culling and
+// the pairs it blends.
+template <int B, bool HIST, bool DEPTH = false, bool COUNT = false>
 __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, const TileCtx &c, LdsBatch<B> &s_rec,
                                              uint32_t *s_idx, uint8_t (*s_list)[4][B], float C[3], float &T,
                                              int &last, float *hist, Resident &res, float *s_depth = nullptr,
-                                             float *D = nullptr) {
+                                             float *D = nullptr, uint32_t *n_eval = nullptr,
+                                             uint32_t *n_blend = nullptr) {
   const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
   // canonical once, so the per-pair min needs no quieting of it
   const float amax = __builtin_canonicalizef(o.alpha_max);
@@ -236,6 +239,10 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
       C[1] = __fmaf_rn(w, R.r2.y, C[1]);
       C[2] = __fmaf_rn(w, R.r2.z, C[2]);
       if (DEPTH) *D = __fmaf_rn(w, s_depth[j], *D);
+      if (COUNT) {
+        *n_eval += valid ? 1u : 0u;
+        *n_blend += take ? 1u : 0u;
+      }
       if (HIST && valid && !stop) hist[(b + j) * 256 + threadIdx.x] = take ? T : 0.0f;
       T = take ? Tn : T;
       last = stop ? (int)(b + j - c.start) : last;
@@ -442,9 +449,12 @@ __device__ __forceinline__ float block_sum_fixed(float x, float *s_w) {
   return r;
 }
 
-template <int TW, int TH, int B, bool HIST, bool DEPTH>
+// COUNT (profiling): pair_counts[p] = pairs blended into pixel p,
+// pair_counts[pixels_total + p] = pairs its lane evaluated.
+template <int TW, int TH, int B, bool HIST, bool DEPTH, bool COUNT>
 __global__ __launch_bounds__(kBlock) void k_raster_fwd(KWs ws, KOpts o, int64_t tile_lo, int64_t tile_count,
-                                                       float *images, int n_views, float *depth) {
+                                                       float *images, int n_views, float *depth,
+                                                       uint32_t *pair_counts) {
   __shared__ LdsBatch<B> s_rec;
   __shared__ float s_depth[DEPTH ? B : 1];
   __shared__ uint8_t s_list[4][4][B];  // [wavefront][sub-block][entry index in the batch]
@@ -459,7 +469,9 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(KWs ws, KOpts o, int64_t 
   int last;
   Resident res;
   float D = 0.0f;
-  tile_forward<B, HIST, DEPTH>(ws, o, c, s_rec, nullptr, s_list, C, T, last, ws.history, res, s_depth, &D);
+  uint32_t n_eval = 0u, n_blend = 0u;
+  tile_forward<B, HIST, DEPTH, COUNT>(ws, o, c, s_rec, nullptr, s_list, C, T, last, ws.history, res, s_depth, &D,
+                                      &n_eval, &n_blend);
   if (c.inside) {
     const int64_t P = (int64_t)c.vi.W * c.vi.H;
     float *img = images + c.vi.pix_base * 3;
@@ -468,6 +480,10 @@ __global__ __launch_bounds__(kBlock) void k_raster_fwd(KWs ws, KOpts o, int64_t 
     ws.pix_T[c.vi.pix_base + c.pix] = T;
     ws.pix_last[c.vi.pix_base + c.pix] = (uint32_t)last;
     if (DEPTH) depth[c.vi.pix_base + c.pix] = D;
+    if (COUNT) {
+      pair_counts[c.vi.pix_base + c.pix] = n_blend;
+      pair_counts[ws.pixels_total + c.vi.pix_base + c.pix] = n_eval;
+    }
   }
 }
 
@@ -666,21 +682,25 @@ int launch_tile_order(const KWs &ws, void *stream) {
   } while (0)
 
 int launch_raster_fwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t tile_count, float *images,
-                      int n_views, int store_history, int lds_batch, float *depth, void *stream) {
+                      int n_views, int store_history, int lds_batch, float *depth, uint32_t *pair_counts,
+                      void *stream) {
   if (tile_count <= 0) return 0;
   const dim3 grid((unsigned)xcd_grid(tile_count)), block(kBlock);
   hipStream_t s = (hipStream_t)stream;
-#define CALL_FWD(a, b_, B)                                                                                       \
-  do {                                                                                                             \
-    if (depth)                                                                                                     \
-      hipLaunchKernelGGL((k_raster_fwd<a, b_, B, false, true>), grid, block, 0, s, ws, o, tile_lo, tile_count,     \
-                         images, n_views, depth);                                                                  \
-    else if (store_history)                                                                                        \
-      hipLaunchKernelGGL((k_raster_fwd<a, b_, B, true, false>), grid, block, 0, s, ws, o, tile_lo, tile_count,     \
-                         images, n_views, depth);                                                                  \
-    else                                                                                                           \
-      hipLaunchKernelGGL((k_raster_fwd<a, b_, B, false, false>), grid, block, 0, s, ws, o, tile_lo, tile_count,    \
-                         images, n_views, depth);                                                                  \
+#define CALL_FWD(a, b_, B)                                                                                        \
+  do {                                                                                                              \
+    if (pair_counts)                                                                                                \
+      hipLaunchKernelGGL((k_raster_fwd<a, b_, B, false, false, true>), grid, block, 0, s, ws, o, tile_lo,           \
+                         tile_count, images, n_views, depth, pair_counts);                                          \
+    else if (depth)                                                                                                 \
+      hipLaunchKernelGGL((k_raster_fwd<a, b_, B, false, true, false>), grid, block, 0, s, ws, o, tile_lo,           \
+                         tile_count, images, n_views, depth, pair_counts);                                          \
+    else if (store_history)                                                                                         \
+      hipLaunchKernelGGL((k_raster_fwd<a, b_, B, true, false, false>), grid, block, 0, s, ws, o, tile_lo,           \
+                         tile_count, images, n_views, depth, pair_counts);                                          \
+    else                                                                                                            \
+      hipLaunchKernelGGL((k_raster_fwd<a, b_, B, false, false, false>), grid, block, 0, s, ws, o, tile_lo,          \
+                         tile_count, images, n_views, depth, pair_counts);                                          \
   } while (0)
   GSR_TILE_DISPATCH(16, 16, CALL_FWD)
   GSR_TILE_DISPATCH(32, 8, CALL_FWD)

@@ -13,7 +13,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgsr.so")
+# GSR_LIBRARY selects another build of the same library (e.g. one whose host
+# code carries sanitizers); the default is the in-tree libgsr.so.
+LIB_PATH = os.environ.get("GSR_LIBRARY") or os.path.join(HERE, "libgsr.so")
 
 GSR_OK = 0
 GSR_ERR_INVALID_ARG = 1
@@ -103,7 +105,8 @@ class gsr_adam(ctypes.Structure):
 
 
 EXPORTS = (
-    "gsr_last_stage_times", "gsr_adam_step", "gsr_render_depth", "gsr_camera_coverage", "gsr_back_project",
+    "gsr_last_stage_times", "gsr_adam_step", "gsr_render_depth", "gsr_pair_counts", "gsr_camera_coverage",
+    "gsr_back_project",
     "gsr_partition_blocks", "gsr_partition_workspace_size", "gsr_partition_blocks_device",
     "gsr_densify_workspace_size", "gsr_densify_count", "gsr_densify_apply",
     "gsr_default_options", "gsr_plan_create", "gsr_plan_destroy", "gsr_workspace_size",
@@ -160,6 +163,7 @@ def load(build_if_missing: bool = True):
                                     P(gsr_stats), _vp, _vp, _i64, P(gsr_grads), P(gsr_grads), P(gsr_grads), _vp,
                                     _vp, _sz, _vp]
     L.gsr_render_depth.argtypes = [_vp, P(gsr_gaussians), _vp, _vp, _vp, _vp, _sz, _vp]
+    L.gsr_pair_counts.argtypes = [_vp, P(gsr_gaussians), _vp, _vp, _vp, _vp, _sz, _vp]
     L.gsr_camera_coverage.argtypes = [_vp, _vp, _vp, _vp, _i32, _f32, _vp, _vp, _vp, _vp]
     L.gsr_adam_step.argtypes = [_vp, P(gsr_adam), P(gsr_grads), P(gsr_grads), P(gsr_grads), P(gsr_grads), _vp,
                                 _vp]
@@ -249,6 +253,10 @@ def gsr_visibility_mask(plan, g, cams, aabb, view_bits, keep_out, in_block, ws, 
 
 def gsr_render_depth(plan, g, cams, images, depth, ws, ws_bytes, stream):
     _check(load().gsr_render_depth(plan, ctypes.byref(g), cams, images, depth, ws, ws_bytes, stream), plan)
+
+
+def gsr_pair_counts(plan, g, cams, images, counts, ws, ws_bytes, stream):
+    _check(load().gsr_pair_counts(plan, ctypes.byref(g), cams, images, counts, ws, ws_bytes, stream), plan)
 
 
 def gsr_camera_coverage(plan, cams, depth, blocks, n_blocks, tau, counts, ratio, selected, stream):

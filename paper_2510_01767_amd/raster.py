@@ -89,10 +89,19 @@ class Rasterizer:
     """One plan + workspace for a fixed problem shape."""
 
     def __init__(self, n, sh_degree, sizes, mode="plain", tile=(16, 16), bwd="recompute", lds_batch=128,
-                 grid_per_cu=4, capacity=0, history_budget=16 << 30, device="cuda", **conventions):
+                 grid_per_cu=4, capacity=0, history_budget=None, device="cuda", **conventions):
         self.n, self.sh_degree, self.sizes = int(n), int(sh_degree), [tuple(map(int, s)) for s in sizes]
         self.V = len(self.sizes)
         self.device = torch.device(device)
+        if history_budget is None:
+            # the stored blend history is used only where it fits in a quarter
+            # of the device memory free now (otherwise the reverse pass
+            # recomputes the transmittance)
+            history_budget = torch.cuda.mem_get_info(self.device)[0] // 4 if torch.cuda.is_available() else 0
+        # bumped by every call that rewrites the workspace; the autograd
+        # functions compare it to catch a reverse pass whose forward state
+        # was overwritten
+        self.generation = 0
         o = C.gsr_default_options()
         o.mode = C.GSR_MODE_BATCHED if mode == "batched" else C.GSR_MODE_PLAIN
         o.tile_w, o.tile_h = tile
@@ -164,6 +173,7 @@ class Rasterizer:
     # ------------------------------------------------------------ the calls
     def step_l1(self, params, cams, targets, keep=None, stats=True, stream=None):
         """gsr_forward_backward_l1: returns (loss [1], images [3P]); gradients land in self.grads."""
+        self.generation += 1
         C.gsr_forward_backward_l1(self.plan, self.gaussians(params, keep), cams.data_ptr(), targets.data_ptr(),
                                   self.images.data_ptr(), self.loss.data_ptr(), self.grads_struct(),
                                   self.stats_struct(stats), self.ws.data_ptr(), self.ws_bytes,
@@ -171,6 +181,7 @@ class Rasterizer:
         return self.loss, self.images
 
     def forward(self, params, cams, keep=None, T_final=None, last=None, images=None, stream=None):
+        self.generation += 1
         img = self.images if images is None else images
         C.gsr_forward(self.plan, self.gaussians(params, keep), cams.data_ptr(), img.data_ptr(),
                       T_final.data_ptr() if T_final is not None else None,
@@ -179,12 +190,14 @@ class Rasterizer:
         return img
 
     def backward(self, params, cams, dL_dimages, keep=None, grads=None, stats=True, stream=None):
+        self.generation += 1
         C.gsr_backward(self.plan, self.gaussians(params, keep), cams.data_ptr(), dL_dimages.data_ptr(),
                        self.grads_struct(grads), self.stats_struct(stats), self.ws.data_ptr(), self.ws_bytes,
                        self.stream_handle(stream))
         return self.grads if grads is None else grads
 
     def visibility_mask(self, params, cams, aabb=None, keep=None, stream=None):
+        self.generation += 1
         bits = torch.zeros(self.n, dtype=torch.int32, device=self.device)
         keep_out = torch.zeros(self.n, dtype=torch.uint8, device=self.device)
         inb = torch.zeros(self.n, dtype=torch.uint8, device=self.device)
@@ -195,18 +208,21 @@ class Rasterizer:
         return bits, keep_out, (inb if aabb is not None else None)
 
     def capture(self, params, cams, targets, keep=None, stats=True, stream=None):
+        self.generation += 1
         C.gsr_graph_capture(self.plan, self.gaussians(params, keep), cams.data_ptr(), targets.data_ptr(),
                             self.images.data_ptr(), self.loss.data_ptr(), self.grads_struct(),
                             self.stats_struct(stats), self.ws.data_ptr(), self.ws_bytes,
                             self.stream_handle(stream))
 
     def launch(self, stream=None):
+        self.generation += 1
         C.gsr_graph_launch(self.plan, self.stream_handle(stream))
 
     def counts(self, stream=None, check=True) -> C.gsr_counts:
         return C.gsr_query_counts(self.plan, self.ws.data_ptr(), self.stream_handle(stream), check)
 
     def autotune(self, params, cams, targets, reps=3, stream=None):
+        self.generation += 1
         best, ms = C.gsr_autotune(self.plan, self.gaussians(params), cams.data_ptr(), targets.data_ptr(),
                                   self.images.data_ptr(), self.loss.data_ptr(), self.grads_struct(),
                                   self.ws.data_ptr(), self.ws_bytes, reps, self.stream_handle(stream))
@@ -227,11 +243,22 @@ class Rasterizer:
 
     def render_depth(self, params, cams, keep=None, images=None, stream=None):
         """gsr_render_depth: (images [3P], depth [P]) with D = sum_i d_i alpha_i T_i per pixel."""
+        self.generation += 1
         img = self.images if images is None else images
         depth = torch.empty(self.pixels, dtype=torch.float32, device=self.device)
         C.gsr_render_depth(self.plan, self.gaussians(params, keep), cams.data_ptr(), img.data_ptr(),
                            depth.data_ptr(), self.ws.data_ptr(), self.ws_bytes, self.stream_handle(stream))
         return img, depth
+
+    def pair_counts(self, params, cams, keep=None, images=None, stream=None):
+        """gsr_pair_counts (profiling): per pixel, the pairs blended and the pairs evaluated
+        after the culling; returns (blended [P], evaluated [P]) as int32 views of u32."""
+        self.generation += 1
+        img = self.images if images is None else images
+        counts = torch.empty(2 * self.pixels, dtype=torch.int32, device=self.device)
+        C.gsr_pair_counts(self.plan, self.gaussians(params, keep), cams.data_ptr(), img.data_ptr(),
+                          counts.data_ptr(), self.ws.data_ptr(), self.ws_bytes, self.stream_handle(stream))
+        return counts[:self.pixels], counts[self.pixels:]
 
     def camera_coverage(self, cams, depth, blocks, tau=0.1, stream=None):
         """gsr_camera_coverage: counts [V][M] (int32 view of u32), ratio V_{c,b} [V][M], selected [V][M]."""
@@ -272,15 +299,18 @@ class Rasterizer:
 
 class RasterizeL1Fn(torch.autograd.Function):
     """L1 training step as an autograd op: forward runs the fused
-    gsr_forward_backward_l1 and keeps its gradients; backward scales them by
-    the incoming gradient of the loss.  The images are a non-differentiable
-    side output."""
+    gsr_forward_backward_l1 and keeps its gradients (copies, so later calls
+    on the same Rasterizer do not change them); backward scales them by the
+    incoming gradient of the loss.  The images are a non-differentiable side
+    output.  The step's capacity and finiteness flags are checked before
+    returning (one synchronisation): an overflowing step raises GsrError."""
 
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, sh, rast: Rasterizer, cams, targets):
         params = dict(means=means.contiguous(), log_scales=log_scales.contiguous(), quats=quats.contiguous(),
                       opacity_logits=opacity_logits.contiguous(), sh=sh.contiguous())
         loss, images = rast.step_l1(params, cams, targets)
+        rast.counts()
         g = [rast.grads[k].clone() for k in PARAM_NAMES]
         ctx.save_for_backward(*g)
         ctx.mark_non_differentiable(images)
@@ -292,21 +322,40 @@ class RasterizeL1Fn(torch.autograd.Function):
         return tuple(x * grad_loss for x in g) + (None, None, None)
 
 
+class StaleForwardError(RuntimeError):
+    """The reverse pass of a render whose forward state (kept in the
+    Rasterizer's workspace) was overwritten by a later call."""
+
+
 class RasterizeFn(torch.autograd.Function):
     """Images as a differentiable function of the parameters (gsr_forward /
-    gsr_backward with an arbitrary image gradient)."""
+    gsr_backward with an arbitrary image gradient).
+
+    The reverse pass reads the forward's state from the Rasterizer's
+    workspace (records, tile lists, per-pixel T_final and `last`).  Each
+    render stamps the Rasterizer's generation; backward raises
+    StaleForwardError if any call rewrote the workspace since, rather than
+    returning gradients of another render.  One Rasterizer per render that
+    must stay differentiable (or backward before the next render) avoids it.
+    The capacity and finiteness flags are checked before returning."""
 
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, sh, rast: Rasterizer, cams):
         params = dict(means=means.contiguous(), log_scales=log_scales.contiguous(), quats=quats.contiguous(),
                       opacity_logits=opacity_logits.contiguous(), sh=sh.contiguous())
         img = rast.forward(params, cams).clone()
+        rast.counts()
         ctx.rast, ctx.params, ctx.cams = rast, params, cams
+        ctx.generation = rast.generation
         return img
 
     @staticmethod
     def backward(ctx, grad_images):
         rast = ctx.rast
+        if rast.generation != ctx.generation:
+            raise StaleForwardError("the Rasterizer's workspace was rewritten after this render's forward "
+                                    f"(generation {ctx.generation} -> {rast.generation}); its reverse pass "
+                                    "cannot run")
         grads = rast.backward(ctx.params, ctx.cams, grad_images.contiguous())
         return tuple(grads[k].clone() for k in PARAM_NAMES) + (None, None)
 

@@ -376,6 +376,23 @@ def small_ragged(seed=SEED_BASE + 100, n=3000, sh_degree=3, sizes=((150, 97), (6
                  seed, [-0.5, -0.5, -1.0, 0.5, 0.5, 1.0], {})
 
 
+def dense_cloud(seed=SEED_BASE + 101, n=400_000, sizes=((256, 256), (200, 136))):
+    """Long tile lists for the sort: a Gaussian cloud N(0, 0.5^2) per axis
+    (clipped to +-1.5) seen from distance 4 by two small views, so that the
+    central tiles list tens of thousands of entries and the outer ones a
+    few, covering every length class of the per-tile sort.  SH degree 0."""
+    rng = np.random.default_rng(seed)
+    means = np.clip(rng.normal(0.0, 0.5, (3, n)), -1.5, 1.5)
+    attrs = _attributes(rng, n, 0)
+    cams = []
+    for k, (W, H) in enumerate(sizes):
+        ang = 0.5 * k
+        eye = (4.0 * math.sin(ang), 0.3 * k, -4.0 * math.cos(ang))
+        cams.append(look_at(eye, (0.0, 0.0, 0.0), W, H, float(W)))
+    return _pack(f"dense-cloud-{n // 1000}k-sh0-{len(sizes)}views", means, attrs, 0, cams, seed,
+                 [-1.5, -1.5, -1.5, 1.5, 1.5, 1.5], {})
+
+
 CONFIGS = {0: config0, 1: config1, 2: config2, 3: config3, 4: config4}
 
 

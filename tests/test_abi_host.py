@@ -195,3 +195,24 @@ def test_bench_refuses_several_gpus():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_bench_byte_model_matches_the_per_unit_budget():
+    """The algorithmic byte model of bench.py: per visible (view, Gaussian)
+    the plain form moves 1100 B at SH degree 3 and 380 B at degree 0; the
+    batched form reads the geometry once (40 B per Gaussian) and writes each
+    visible Gaussian's gradients once; the fused raster moves 80 B per
+    intersection, 52 B per pixel and 36 B per visible record."""
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    for K, F, cv in ((48, 59, 1100), (3, 14, 380)):
+        assert b.b_alg_plain(0, K, F, 1, 1, 0, 0) == cv
+        assert b.b_alg_plain(1, K, F, 1, 0, 0, 0) == 12
+    assert b.b_alg_plain(0, 48, 59, 1, 0, 1, 0) == 140 and b.b_alg_plain(0, 48, 59, 1, 0, 0, 1) == 52
+    assert b.b_alg_batched(1, 0, 48, 59, 0, 0, 0) == 40
+    assert b.b_alg_batched(0, 1, 48, 59, 0, 0, 0) == 4 + 4 * 48 + 8 * 59 + 16
+    assert b.b_alg_batched(0, 0, 48, 59, 1, 0, 0) == 152
+    assert b.b_alg_fused(1, 0, 0) == 36 and b.b_alg_fused(0, 1, 0) == 80 and b.b_alg_fused(0, 0, 1) == 52

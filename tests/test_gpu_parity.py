@@ -358,6 +358,81 @@ def test_autograd_function_returns_library_gradients(ragged):
         assert np.linalg.norm(a - b) <= 1e-6 * max(np.linalg.norm(b), 1e-30), k
 
 
+def test_render_backward_after_a_second_render_raises_or_matches_oracle(ragged):
+    """Two renders on one Rasterizer, then the first one's backward: it must
+    raise (its forward state was overwritten), never return another render's
+    gradients; the second one's backward gives the oracle's gradients."""
+    announce("autograd: stale forward")
+    from paper_2510_01767_amd.raster import StaleForwardError, render
+    r, params, cams, targets = setup(ragged, mode="batched")
+    leaves1 = {k: v.clone().requires_grad_(True) for k, v in params.items()}
+    leaves2 = {k: v.clone().requires_grad_(True) for k, v in params.items()}
+    img1 = render(leaves1, r, cams)
+    img2 = render(leaves2, r, cams)
+    assert torch.equal(img1, img2)
+    # dL/dimage of the L1 loss of the oracle's definition (mean over views of the per-view mean)
+    sizes = r.sizes
+    w = torch.cat([torch.full((3 * W * H,), 1.0 / (3 * W * H * len(sizes)), device="cuda") for W, H in sizes])
+    loss1 = ((img1 - targets).abs() * w).sum()
+    loss2 = ((img2 - targets).abs() * w).sum()
+    with pytest.raises(StaleForwardError):
+        loss1.backward()
+    loss2.backward()
+    ora = ora_step(ragged)
+    ex = parity.excluded_gaussians(ora, ragged.n, parity.opts_for(), ragged.targets)
+    g = {k: v.grad for k, v in leaves2.items()}
+    parity.compare_grads(parity.gpu_grad_groups(g), ora["grads"], ex)
+    # a render followed by its own backward before the next render is fine
+    leaves3 = {k: v.clone().requires_grad_(True) for k, v in params.items()}
+    ((render(leaves3, r, cams) - targets).abs() * w).sum().backward()
+    for k in leaves3:
+        assert torch.allclose(leaves3[k].grad, leaves2[k].grad, rtol=1e-5, atol=1e-12), k
+
+
+def test_autograd_functions_raise_on_capacity_overflow(ragged):
+    announce("autograd: overflow")
+    from paper_2510_01767_amd.raster import render, render_l1
+    r, params, cams, targets = setup(ragged, mode="batched", capacity=1000)
+    leaves = {k: v.clone().requires_grad_(True) for k, v in params.items()}
+    with pytest.raises(C.GsrError) as e:
+        render_l1(leaves, r, cams, targets)
+    assert e.value.status == C.GSR_ERR_CAPACITY
+    with pytest.raises(C.GsrError) as e:
+        render(leaves, r, cams)
+    assert e.value.status == C.GSR_ERR_CAPACITY
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 8)])
+def test_pair_counts_match_oracle(ragged, tile):
+    """Per pixel, the pairs the profiling forward counts as blended equal the
+    oracle's blended entries (the compositing weights alpha T > 0 before the
+    stop), on pixels without ambiguous decisions; evaluated pairs lie between
+    the blended ones and the walked list length `last`."""
+    announce("pair counts", tile)
+    r, params, cams, targets = setup(ragged, mode="batched", tile=tile)
+    blended, evaluated = r.pair_counts(params, cams)
+    torch.cuda.synchronize()
+    P = oracle.Params.from_scene(ragged)
+    fo = oracle.forward(P, ragged.cameras, parity.opts_for(tile))
+    o = 0
+    bl, ev = blended.cpu().numpy(), evaluated.cpu().numpy()
+    last = r.ws_tensor("pix_last", torch.int32, r.pixels).cpu().numpy()
+    for v, (W, H) in enumerate(r.sizes):
+        amb = fo["ambiguous"][v].astype(bool).ravel()
+        # the oracle's blended count: entries with alpha >= alpha_min before the stop
+        n_bl = fo["blended"][v].ravel()
+        b_ = bl[o:o + W * H]
+        assert np.array_equal(b_[~amb], n_bl[~amb]), v
+        e_ = ev[o:o + W * H]
+        assert np.all(e_ >= b_) and np.all(e_ <= last[o:o + W * H])
+        o += W * H
+    assert int(bl.sum()) > 0
+    # the reverse pass cannot follow a profiling render
+    with pytest.raises(C.GsrError) as e:
+        r.backward(params, cams, torch.zeros_like(r.images))
+    assert e.value.status == C.GSR_ERR_STATE
+
+
 def test_gpu_gradient_agrees_with_oracle_finite_differences():
     """GPU analytic gradient vs central differences of the FP64 oracle loss."""
     announce("gpu vs oracle FD")

@@ -215,3 +215,16 @@ def test_flagged_pixel_removes_only_gaussians_reaching_it():
     assert list(hit) == [True, False, True]
     # no flagged pixel: nothing removed
     assert not oracle.touching(fo, [np.zeros((128, 128), bool)], O).any()
+
+
+def test_blended_count_of_the_early_stop_stack():
+    """Five identical Gaussians with alpha 0.95 on one pixel centre: three are
+    blended (T = 0.05^3 = 1.25e-4 >= 1e-4), the fourth would take T below
+    1e-4 and stops the pixel; `last` counts the three processed entries and
+    the blended count is 3 (the closed form of the early-stop golden)."""
+    zs = [0.0, 0.1, 0.2, 0.3, 0.4]
+    means = [[px_to_x(64.5, Z + z), px_to_x(64.5, Z + z), z] for z in zs]
+    f = fwd(params(means, opacities=[0.95] * 5))
+    assert f["blended"][0][64, 64] == 3
+    assert f["last"][0][64, 64] == 3
+    np.testing.assert_allclose(f["T_final"][0][64, 64], 0.05 ** 3, rtol=1e-12)

@@ -503,7 +503,7 @@ def test_densification_statistic_matches_fd_in_screen_space(tiny):
             L.ora_render(ctypes.byref(O), W, H, _p(rv, oracle._i64), _p(res["bins"]["values"], oracle._i64), n * V,
                          _p(mean2d, oracle._d), _p(R["conic"], oracle._d), _p(R["opacity"], oracle._d),
                          _p(R["color"], oracle._d), _p(R["depth"], oracle._d), None, 0.0, 0.0, 0.0,
-                         _p(img, oracle._d), _p(T, oracle._d), _p(la, oracle._i32), None, None, None)
+                         _p(img, oracle._d), _p(T, oracle._d), _p(la, oracle._i32), None, None, None, None)
             total += np.abs(img - targets[v]).mean()
         return total / V
 
