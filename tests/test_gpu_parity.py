@@ -385,8 +385,9 @@ def test_render_backward_after_a_second_render_raises_or_matches_oracle(ragged):
     # a render followed by its own backward before the next render is fine
     leaves3 = {k: v.clone().requires_grad_(True) for k, v in params.items()}
     ((render(leaves3, r, cams) - targets).abs() * w).sum().backward()
-    for k in leaves3:
-        assert torch.allclose(leaves3[k].grad, leaves2[k].grad, rtol=1e-5, atol=1e-12), k
+    for k in leaves3:  # equal up to the order of float atomics
+        a, b = leaves3[k].grad, leaves2[k].grad
+        assert float(torch.linalg.norm(a - b)) <= 1e-6 * float(torch.linalg.norm(b)), k
 
 
 def test_autograd_functions_raise_on_capacity_overflow(ragged):
