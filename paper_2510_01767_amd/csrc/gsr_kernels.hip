@@ -587,19 +587,27 @@ __device__ __forceinline__ int next_pow2(int x) {
   return p;
 }
 
-// Merge two sorted runs A[0, la), B[0, lb) into out; output element k is
-// found by a co-rank binary search (keys are unique).
+// Merge two sorted runs A[0, la), B[0, lb) into out.  Each thread takes a
+// contiguous chunk of kMergeChunk outputs: one co-rank binary search finds
+// where the chunk starts in A and in B (keys are unique), then the chunk is
+// merged sequentially.
+constexpr int kMergeChunk = 16;
+
 __device__ void merge_runs(const uint64_t *A, int64_t la, const uint64_t *B, int64_t lb, uint64_t *out) {
-  for (int64_t k = threadIdx.x; k < la + lb; k += blockDim.x) {
-    int64_t lo = k > lb ? k - lb : 0, hi = k < la ? k : la;
+  const int64_t total = la + lb;
+  for (int64_t k0 = (int64_t)threadIdx.x * kMergeChunk; k0 < total; k0 += (int64_t)blockDim.x * kMergeChunk) {
+    int64_t lo = k0 > lb ? k0 - lb : 0, hi = k0 < la ? k0 : la;
     while (lo < hi) {
       const int64_t ia = (lo + hi) >> 1;
-      if (A[ia] < B[k - ia - 1]) lo = ia + 1;
+      if (A[ia] < B[k0 - ia - 1]) lo = ia + 1;
       else hi = ia;
     }
-    const int64_t ia = lo, ib = k - lo;
-    const bool takeA = ib >= lb || (ia < la && A[ia] < B[ib]);
-    out[k] = takeA ? A[ia] : B[ib];
+    int64_t ia = lo, ib = k0 - lo;
+    const int64_t k1 = min(k0 + (int64_t)kMergeChunk, total);
+    for (int64_t k = k0; k < k1; k++) {
+      const bool takeA = ib >= lb || (ia < la && A[ia] < B[ib]);
+      out[k] = takeA ? A[ia++] : B[ib++];
+    }
   }
 }
 
