@@ -222,6 +222,20 @@ gsr_status gsr_forward_backward_l1(gsr_plan *plan, const gsr_gaussians *g,
                                    float *loss, const gsr_grads *grads, const gsr_stats *stats,
                                    void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): the fused step of
+ * gsr_forward_backward_l1, same arguments and results, with the workspace
+ * taken from a static device array of GSR_STATIC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends.  No device
+ * memory is allocated or freed; no stage timing (profile_stages is ignored).
+ * GSR_ERR_WORKSPACE_TOO_SMALL when gsr_workspace_size exceeds the array.
+ * Calls on one GPU share the array: calls that overlap on one GPU race.  The
+ * stream must belong to the current device. */
+#define GSR_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+gsr_status gsr_forward_backward_l1_static(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams,
+                                          const float *targets, float *images, float *loss,
+                                          const gsr_grads *grads, const gsr_stats *stats, void *stream);
+
 /* Visibility cropping over the plan's views (Sec. 3.3): view_bits[i] has bit
  * v set when Gaussian i is visible in view v; keep_out[i] = (view_bits != 0);
  * in_block[i] = 1 when the mean lies in the half-open box aabb = (xmin, ymin,

@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libgsr.so")
 SOURCES = [os.path.join(CSRC, "gsr_api.cpp"), os.path.join(CSRC, "gsr_kernels.hip"),
            os.path.join(CSRC, "gsr_raster.hip"), os.path.join(CSRC, "gsr_optim.hip"),
            os.path.join(CSRC, "gsr_fcs.hip"), os.path.join(CSRC, "gsr_partition.cpp"),
-           os.path.join(CSRC, "gsr_densify.hip")]
+           os.path.join(CSRC, "gsr_densify.hip"), os.path.join(CSRC, "gsr_static.hip")]
 HEADERS = [os.path.join(ROOT, "include", "gsr.h"), os.path.join(CSRC, "gsr_internal.h"),
            os.path.join(CSRC, "gsr_device.h"), os.path.join(CSRC, "gsr_stages.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -664,6 +664,28 @@ gsr_status gsr_forward_backward_l1(gsr_plan *plan, const gsr_gaussians *g, const
   return enqueue_batched_l1(plan, g, cams, targets, images, loss, grads, stats, k, stream);
 }
 
+}  // extern "C"
+
+namespace gsr {
+
+gsr_status fused_l1_no_events(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams, const float *targets,
+                              float *images, float *loss, const gsr_grads *grads, const gsr_stats *stats, void *ws,
+                              size_t ws_bytes, void *stream) {
+  if (!plan) return GSR_ERR_INVALID_ARG;
+  const bool was = plan->capturing;
+  plan->capturing = true;  // suppresses stage timing, which would create events
+  const gsr_status s = gsr_forward_backward_l1(plan, g, cams, targets, images, loss, grads, stats, ws, ws_bytes,
+                                               stream);
+  plan->capturing = was;
+  return s;
+}
+
+gsr_status plan_error(gsr_plan *plan, gsr_status s, const char *msg) { return fail(plan, s, msg); }
+
+}  // namespace gsr
+
+extern "C" {
+
 gsr_status gsr_visibility_mask(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams, const float *aabb,
                                uint32_t *view_bits, uint8_t *keep_out, uint8_t *in_block, void *ws, size_t ws_bytes,
                                void *stream) {

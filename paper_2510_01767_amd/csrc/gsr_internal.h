@@ -135,4 +135,13 @@ int launch_copy_pixels(const KWs &ws, float *T_out, uint32_t *last_out, void *st
 int launch_count_visible(const KWs &ws, int64_t n, int n_views, void *stream);
 int launch_tile_order(const KWs &ws, void *stream);
 
+// ------------------------------------------------------- host entry helpers
+// Defined in gsr_api.cpp.  fused_l1_no_events: gsr_forward_backward_l1
+// without stage timing (creates no event).  plan_error: records msg as the
+// plan's last error and returns s.
+gsr_status fused_l1_no_events(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams, const float *targets,
+                              float *images, float *loss, const gsr_grads *grads, const gsr_stats *stats, void *ws,
+                              size_t ws_bytes, void *stream);
+gsr_status plan_error(gsr_plan *plan, gsr_status s, const char *msg);
+
 }  // namespace gsr

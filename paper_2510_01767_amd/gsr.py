@@ -106,7 +106,7 @@ class gsr_adam(ctypes.Structure):
 
 EXPORTS = (
     "gsr_last_stage_times", "gsr_adam_step", "gsr_render_depth", "gsr_pair_counts", "gsr_camera_coverage",
-    "gsr_back_project",
+    "gsr_back_project", "gsr_forward_backward_l1_static",
     "gsr_partition_blocks", "gsr_partition_workspace_size", "gsr_partition_blocks_device",
     "gsr_densify_workspace_size", "gsr_densify_count", "gsr_densify_apply",
     "gsr_default_options", "gsr_plan_create", "gsr_plan_destroy", "gsr_workspace_size",
@@ -164,6 +164,8 @@ def load(build_if_missing: bool = True):
                                     _vp, _sz, _vp]
     L.gsr_render_depth.argtypes = [_vp, P(gsr_gaussians), _vp, _vp, _vp, _vp, _sz, _vp]
     L.gsr_pair_counts.argtypes = [_vp, P(gsr_gaussians), _vp, _vp, _vp, _vp, _sz, _vp]
+    L.gsr_forward_backward_l1_static.argtypes = [_vp, P(gsr_gaussians), _vp, _vp, _vp, _vp, P(gsr_grads),
+                                                 P(gsr_stats), _vp]
     L.gsr_camera_coverage.argtypes = [_vp, _vp, _vp, _vp, _i32, _f32, _vp, _vp, _vp, _vp]
     L.gsr_adam_step.argtypes = [_vp, P(gsr_adam), P(gsr_grads), P(gsr_grads), P(gsr_grads), P(gsr_grads), _vp,
                                 _vp]
@@ -253,6 +255,15 @@ def gsr_visibility_mask(plan, g, cams, aabb, view_bits, keep_out, in_block, ws, 
 
 def gsr_render_depth(plan, g, cams, images, depth, ws, ws_bytes, stream):
     _check(load().gsr_render_depth(plan, ctypes.byref(g), cams, images, depth, ws, ws_bytes, stream), plan)
+
+
+GSR_STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def gsr_forward_backward_l1_static(plan, g, cams, targets, images, loss, grads, stats, stream):
+    _check(load().gsr_forward_backward_l1_static(plan, ctypes.byref(g), cams, targets, images, loss,
+                                                 ctypes.byref(grads), ctypes.byref(stats) if stats else None,
+                                                 stream), plan)
 
 
 def gsr_pair_counts(plan, g, cams, images, counts, ws, ws_bytes, stream):

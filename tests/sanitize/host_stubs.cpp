@@ -60,9 +60,9 @@ int launch_coverage(const ViewTable &, const gsr_camera *, const float *, const 
 
 }  // namespace gsr
 
-// The densification entry points live with their kernels; this host-only
-// build carries placeholders so that the binding's declarations resolve (the
-// sanitized suites do not call them).
+// The densification and allocation-free entry points live with their device
+// code; this host-only build carries placeholders so that the binding's
+// declarations resolve (the sanitized suites do not call them).
 extern "C" gsr_status gsr_densify_workspace_size(int64_t, size_t *) { return GSR_ERR_HIP; }
 extern "C" gsr_status gsr_densify_count(int64_t, int32_t, const gsr_densify_opts *, const gsr_gaussians *,
                                         const gsr_stats *, const uint8_t *, void *, size_t, void *, int64_t *) {
@@ -72,5 +72,10 @@ extern "C" gsr_status gsr_densify_apply(int64_t, int32_t, const gsr_densify_opts
                                         const gsr_grads *, const gsr_grads *, const gsr_stats *, const uint8_t *,
                                         const float *, int64_t, const gsr_grads *, const gsr_grads *,
                                         const gsr_grads *, int64_t *, void *, size_t, void *) {
+  return GSR_ERR_HIP;
+}
+extern "C" gsr_status gsr_forward_backward_l1_static(gsr_plan *, const gsr_gaussians *, const gsr_camera *,
+                                                      const float *, float *, float *, const gsr_grads *,
+                                                      const gsr_stats *, void *) {
   return GSR_ERR_HIP;
 }
