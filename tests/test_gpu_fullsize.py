@@ -253,7 +253,7 @@ def test_config4_window_matches_oracle():
         a_, b_ = gg[:, k], go[:, k]
         rel = np.linalg.norm(a_ - b_) / max(np.linalg.norm(b_), 1e-300)
         rms = np.sqrt(np.mean(b_ ** 2))
-        excess = np.abs(a_ - b_) - 1e-3 * (np.abs(b_) + 1e-2 * rms)
+        excess = np.abs(a_ - b_) - 1e-3 * (np.abs(b_) + parity.ELEM_FLOOR_DEEP * rms)
         if excess.max() > 0:
             w = np.argsort(-excess)[:5]
             print("component", k, "elements over", int((excess > 0).sum()), "of", excess.size, "rms", rms,
