@@ -42,7 +42,7 @@ FP32_PEAK_TFLOPS = 157.3
 FLOPS_FWD_PAIR = 21
 FLOPS_BWD_PAIR = 58
 RASTER_SOURCES = ["paper_2510_01767_amd/csrc/gsr_raster.hip", "paper_2510_01767_amd/csrc/gsr_device.h",
-                  "paper_2510_01767_amd/csrc/gsr_internal.h"]
+                  "paper_2510_01767_amd/csrc/gsr_internal.h", "paper_2510_01767_amd/csrc/gsr_cull.h"]
 TRAFFIC_SUMMARY = "profiles/hbm_traffic_city-block-3000k-16views.md"
 
 

@@ -14,7 +14,8 @@ SOURCES = [os.path.join(CSRC, "gsr_api.cpp"), os.path.join(CSRC, "gsr_kernels.hi
            os.path.join(CSRC, "gsr_fcs.hip"), os.path.join(CSRC, "gsr_partition.cpp"),
            os.path.join(CSRC, "gsr_densify.hip"), os.path.join(CSRC, "gsr_static.hip")]
 HEADERS = [os.path.join(ROOT, "include", "gsr.h"), os.path.join(CSRC, "gsr_internal.h"),
-           os.path.join(CSRC, "gsr_device.h"), os.path.join(CSRC, "gsr_stages.h")]
+           os.path.join(CSRC, "gsr_device.h"), os.path.join(CSRC, "gsr_stages.h"),
+           os.path.join(CSRC, "gsr_cull.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

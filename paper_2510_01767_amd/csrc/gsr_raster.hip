@@ -22,6 +22,7 @@
 // atomic per (entry, component).
 #include <hip/hip_runtime.h>
 
+#include "gsr_cull.h"
 #include "gsr_device.h"
 
 namespace gsr {
@@ -70,11 +71,6 @@ __device__ __forceinline__ void tile_ctx(const KWs &ws, const ViewInfo *views, i
   c.wy1 = c.wy0 + (float)(kRows - 1);
 }
 
-struct LdsRec {
-  float4 r0, r1, r2;  // mean (hi, lo), base-2 exponent coefficients + opacity, colour + base-2 pmin
-  float reach;
-};
-
 // A batch of records in LDS as separate arrays: the four 16-lane rows of a
 // wavefront read four different entries at once, which in a 64-byte record
 // array would start on the same banks.
@@ -94,42 +90,6 @@ __device__ __forceinline__ LdsRec rec_at(const LdsBatch<B> &s, int j) {
   return R;
 }
 
-// Can the entry's alpha reach alpha_min at some pixel centre of this lane's
-// wavefront strip?  Two tests against the box of the strip's pixel centres:
-// the circle of radius `reach`, then the ellipse itself.  alpha >= alpha_min
-// needs the base-2 exponent q(d) = a dx^2 + b dx dy + c dy^2 >= pmin2
-// (slack included).  q is concave with its maximum 0 at the mean, so over a
-// box that does not hold the mean its maximum lies on an edge that faces the
-// mean, where q is a 1D quadratic maximised in closed form.  The box offsets
-// are formed like the per-pixel offsets ((centre - hi) - lo), so they differ
-// from what a pixel evaluates only by relative roundings of a few 1e-7; the
-// threshold carries 1e-4 relative and 1e-4 log2(e) / 2 absolute on top.
-__device__ __forceinline__ bool reaches_box(const LdsRec &R, float bx0, float bx1, float by0, float by1) {
-  const float reach = R.reach;
-  if (reach < 0.0f) return false;
-  const float mx = R.r0.x + R.r0.z, my = R.r0.y + R.r0.w;
-  const float ddx = fmaxf(0.0f, fmaxf(bx0 - mx, mx - bx1));
-  const float ddy = fmaxf(0.0f, fmaxf(by0 - my, my - by1));
-  if (ddx * ddx + ddy * ddy > reach * reach) return false;
-  const float x0 = (bx0 - R.r0.x) - R.r0.z, x1 = (bx1 - R.r0.x) - R.r0.z;
-  const float y0 = (by0 - R.r0.y) - R.r0.w, y1 = (by1 - R.r0.y) - R.r0.w;
-  const bool out_x = x0 > 0.0f || x1 < 0.0f, out_y = y0 > 0.0f || y1 < 0.0f;
-  if (!out_x && !out_y) return true;
-  const float a = R.r1.x, b = R.r1.y, cc = R.r1.z;
-  float qmax = -3.0e38f;
-  if (out_x) {
-    const float X = x0 > 0.0f ? x0 : x1;
-    const float Y = fminf(fmaxf(-b * X / (2.0f * cc), y0), y1);
-    qmax = fmaxf(qmax, a * X * X + b * X * Y + cc * Y * Y);
-  }
-  if (out_y) {
-    const float Y = y0 > 0.0f ? y0 : y1;
-    const float X = fminf(fmaxf(-b * Y / (2.0f * a), x0), x1);
-    qmax = fmaxf(qmax, a * X * X + b * X * Y + cc * Y * Y);
-  }
-  return qmax >= R.r2.w * 1.0001f - 7.2135e-5f;
-}
-
 template <int B>
 __device__ __forceinline__ void load_batch(const KWs &ws, int64_t lo, int nb, LdsBatch<B> &s_rec, uint32_t *s_idx,
                                            float *s_depth = nullptr) {
@@ -147,9 +107,10 @@ __device__ __forceinline__ void load_batch(const KWs &ws, int64_t lo, int nb, Ld
 }
 
 // The kept entries of the batch for each of the wavefront's four
-// sub-blocks, in list order: an entry is tested against the strip, then
-// against each sub-block.  lists[q] of sub-block q gets cnt[q] entries;
-// returns the count of this lane's own sub-block.
+// sub-blocks, in list order: an entry is tested against the strip's circle,
+// then each band of sub-blocks gets its interval and each sub-block two
+// compares.  lists[q] of sub-block q gets cnt[q] entries; returns the count
+// of this lane's own sub-block.
 template <int B>
 __device__ __forceinline__ int sub_lists(const LdsBatch<B> &s_rec, int nb, const TileCtx &c, uint8_t (*lists)[B],
                                          int cnt[4]) {
@@ -160,11 +121,15 @@ __device__ __forceinline__ int sub_lists(const LdsBatch<B> &s_rec, int nb, const
   for (int jb = 0; jb < nb; jb += 64) {
     const int j = jb + lane;
     const LdsRec R = rec_at(s_rec, j < nb ? j : 0);
-    const bool strip = j < nb && reaches_box(R, c.wx0, c.wx1, c.wy0, c.wy1);
+    const bool strip = j < nb && reaches_strip(R, c.wx0, c.wx1, c.wy0, c.wy1);
+    const ReachShape S = reach_shape(R);
+    float xl = 3.0e38f, xr = -3.0e38f;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       const float bx0 = c.wx0 + (float)((q % c.snx) * c.sw), by0 = c.wy0 + (float)((q / c.snx) * c.sh);
-      const bool keep = strip && reaches_box(R, bx0, bx0 + (float)(c.sw - 1), by0, by0 + (float)(c.sh - 1));
+      if (q % c.snx == 0) band_interval(R, S, by0, by0 + (float)(c.sh - 1), xl, xr);
+      const float x0 = (bx0 - R.r0.x) - R.r0.z, x1 = ((bx0 + (float)(c.sw - 1)) - R.r0.x) - R.r0.z;
+      const bool keep = strip && (S.thin || (x1 >= xl && x0 <= xr));
       const uint64_t m = __ballot(keep);
       if (keep) lists[q][cnt[q] + __popcll(m & below)] = (uint8_t)j;
       cnt[q] += __popcll(m);
