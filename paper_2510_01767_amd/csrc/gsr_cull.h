@@ -34,6 +34,8 @@ struct LdsRec {
 //    from the exact q of the stored coefficients by at most ~4 ulp of its
 //    terms' magnitudes, which on the ellipse stay below |p_s| m;
 //  * det in double, where the float products are exact (thin ellipses);
+//  * reciprocals and square roots by the hardware instructions (1 ulp),
+//    far inside the pads below;
 //  * the interval is padded by 1e-3 px, 1e-3 of the central half-chord
 //    kap ey (the square root's error near a tangent) and 1e-5 of the shear
 //    term;
@@ -59,10 +61,10 @@ __device__ __forceinline__ ReachShape reach_shape(const LdsRec &R) {
   const float ia = -0.5f * __builtin_amdgcn_rcpf(a);
   const float q4 = 4.0f * ps * inv_det;
   S.ey2 = q4 * a;
-  S.ey = __builtin_sqrtf(S.ey2);
+  S.ey = __builtin_amdgcn_sqrtf(S.ey2);
   S.sig = b * ia;
-  S.kap = __builtin_sqrtf(detf) * ia;
-  S.yr = (-0.5f * b * __builtin_amdgcn_rcpf(c)) * __builtin_sqrtf(q4 * c);
+  S.kap = __builtin_amdgcn_sqrtf(detf) * ia;
+  S.yr = (-0.5f * b * __builtin_amdgcn_rcpf(c)) * __builtin_amdgcn_sqrtf(q4 * c);
   return S;
 }
 
@@ -72,8 +74,8 @@ __device__ __forceinline__ void band_interval(const LdsRec &R, const ReachShape 
                                               float &xr) {
   const float y0 = (by0 - R.r0.y) - R.r0.w, y1 = (by1 - R.r0.y) - R.r0.w;
   const float ys = __builtin_amdgcn_fmed3f(S.yr, y0, y1), yl = __builtin_amdgcn_fmed3f(-S.yr, y0, y1);
-  const float hr = S.kap * __builtin_sqrtf(fmaxf(0.0f, __fmaf_rn(-ys, ys, S.ey2)));
-  const float hl = S.kap * __builtin_sqrtf(fmaxf(0.0f, __fmaf_rn(-yl, yl, S.ey2)));
+  const float hr = S.kap * __builtin_amdgcn_sqrtf(fmaxf(0.0f, __fmaf_rn(-ys, ys, S.ey2)));
+  const float hl = S.kap * __builtin_amdgcn_sqrtf(fmaxf(0.0f, __fmaf_rn(-yl, yl, S.ey2)));
   const float pad = __fmaf_rn(1.0e-5f * fabsf(S.sig), fmaxf(fabsf(y0), fabsf(y1)),
                               __fmaf_rn(1.0e-3f * S.kap, S.ey, 1.0e-3f));
   const bool miss = y0 > S.ey || y1 < -S.ey;

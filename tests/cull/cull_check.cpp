@@ -4,8 +4,8 @@
 // base-2 exponent coefficients, the alpha_min level with its slack, the reach
 // radius) and random 16 x 4 strips of four 4 x 4 sub-blocks, no sub-block
 // that holds a pixel centre whose float32 exponent passes the per-pair
-// test may be culled.  The device's 1-ulp reciprocal is modelled by nudging
-// each quotient by one ulp either way at random.
+// test may be culled.  The device's 1-ulp reciprocal and square root are
+// modelled by nudging each result by one ulp either way at random.
 //
 // usage: cull_check SEED COUNT  -> prints counts; exit status 1 on a dropped sub-block
 #include <algorithm>
@@ -23,6 +23,11 @@ static float rcp_1ulp(float x) {
   const int s = (int)(g_rng() % 3) - 1;
   return s == 0 ? r : std::nextafter(r, s > 0 ? INFINITY : -INFINITY);
 }
+static float sqrt_1ulp(float x) {
+  const float r = std::sqrt(x);
+  const int s = (int)(g_rng() % 3) - 1;
+  return s == 0 || !(r > 0.0f) || std::isinf(r) ? r : std::nextafter(r, s > 0 ? INFINITY : -INFINITY);
+}
 static float med3(float a, float b, float c) { return std::max(std::min(a, b), std::min(std::max(a, b), c)); }
 
 struct float4 {
@@ -31,6 +36,7 @@ struct float4 {
 #define __device__
 #define __forceinline__ inline
 #define __builtin_amdgcn_rcpf(x) rcp_1ulp(x)
+#define __builtin_amdgcn_sqrtf(x) sqrt_1ulp(x)
 #define __builtin_amdgcn_fmed3f(a, b, c) med3(a, b, c)
 #define __fmaf_rn(a, b, c) std::fmaf(a, b, c)
 #define __fma_rn(a, b, c) std::fma(a, b, c)
