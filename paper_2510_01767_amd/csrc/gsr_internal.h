@@ -28,7 +28,7 @@ struct ViewTable {
 struct WsHeader {
   uint32_t overflow;
   uint32_t nonfinite;
-  uint32_t queue;         // persistent raster work counter
+  uint32_t pad0;
   uint32_t union_count;   // Gaussians visible in >= 1 view
   uint32_t isect_total;
   uint32_t big_count;     // tiles whose lists exceed one wavefront's sort, collected per sort call
@@ -40,6 +40,9 @@ struct WsHeader {
   // bin (descending) and the bins' fill cursors
   uint32_t order_bins[1024];
   uint32_t order_cursor[1024];
+  // persistent raster work counters, one per workgroup class (blockIdx mod
+  // 8), each in a 128-byte line of its own
+  uint32_t queue[8][32];
 };
 constexpr int kOrderBins = 1024;
 

@@ -32,10 +32,10 @@ __global__ void k_setup(ViewTable table, KWs ws, int64_t zlo, int64_t zcount, in
     WsHeader *h = ws.hdr;
     h->overflow = 0;
     h->nonfinite = 0;
-    h->queue = 0;
     h->union_count = 0;
     h->isect_total = 0;
   }
+  if (gid < 8) ws.hdr->queue[gid][0] = 0;
   if (gid < GSR_MAX_VIEWS) {
     ws.hdr->isect[gid] = 0;
     ws.hdr->visible[gid] = 0;

@@ -313,7 +313,7 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
     const uint8_t *mine = s_list[wave][(lane & 63) >> 4];
     while (cnt > 0 && (int)mine[cnt - 1] >= nb_top) cnt--;
     int kmax = max(cnt, __shfl_xor(cnt, 16));  // the longest of the wavefront's four row lists
-    kmax = max(kmax, __shfl_xor(kmax, 32));
+    kmax = __builtin_amdgcn_readfirstlane(max(kmax, __shfl_xor(kmax, 32)));  // uniform: a scalar loop counter
     const int jj_last = active ? last - (int)(lo - c.start) : 0;  // this pixel's entries: jj < jj_last
     for (int k = kmax - 1; k >= 0; k--) {
       const bool valid = k < cnt;
@@ -323,13 +323,15 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
       const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, amax);
       const bool contrib = valid && jj < jj_last && a.alpha >= o.alpha_min;
       if (__ballot(contrib) == 0ull) continue;
-      // Every lane evaluates the partials (all finite: alpha <= 0.99); the
-      // non-contributing ones get zero weights, so they add exact zeros.
+      // Every lane evaluates the partials (all finite: alpha <= 0.99).  The
+      // non-contributing lanes take alpha = 0 here: 1 / (1 - 0) is exactly 1,
+      // so their T and suffix stay as they are and they add exact zeros.
       // 1 / (1 - alpha) by the hardware reciprocal (1 ulp): T and the
       // suffix only feed gradients, never a discrete decision.
-      const float inv_om = __builtin_amdgcn_rcpf(1.0f - a.alpha);
+      const float al = contrib ? a.alpha : 0.0f;
+      const float inv_om = __builtin_amdgcn_rcpf(1.0f - al);
       const float Ti = HIST ? (contrib ? hist[j * 256 + threadIdx.x] : T) : T * inv_om;
-      const float wgt = contrib ? a.alpha * Ti : 0.0f;
+      const float wgt = al * Ti;
       const float col[3] = {R.r2.x, R.r2.y, R.r2.z};
       float v[9];
       const float gc = __fmaf_rn(g[2], col[2], __fmaf_rn(g[1], col[1], g[0] * col[0]));
@@ -348,7 +350,7 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
       v[2] = -0.5f * gp * a.dx * a.dx;
       v[3] = -gp * a.dx * a.dy;
       v[4] = -0.5f * gp * a.dy * a.dy;
-      T = contrib ? Ti : T;
+      T = Ti;
       if (RED == 0) {
         // the row's reduce-scatter, then one device atomic per component from
         // lanes 0..8 of the row into its entry's gradient slot
@@ -511,9 +513,13 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(KWs ws, KOpts o, int64_t 
                               Resident{0, 0, 0});
 }
 
-// Persistent fused forward + L1 + reverse pass.  Workgroups take tiles from
-// ws.hdr->queue (in `order` when given) until the counter passes the last
-// tile; no workgroup ever waits for another.
+// Persistent fused forward + L1 + reverse pass.  Workgroups take tiles
+// (in `order` when given) until their counter passes the last tile; no
+// workgroup ever waits for another.  Workgroup class x = blockIdx mod 8 takes
+// items x, x + 8, x + 16, ... from a counter of its own: the hardware hands
+// consecutive workgroups to the 8 XCDs in turn, so each counter is shared by
+// one XCD's workgroups instead of one counter by the whole chip.  The grid
+// is a multiple of 8, so every class has workgroups and every tile is taken.
 template <int TW, int TH, int B, int RED, bool HIST>
 __global__ __launch_bounds__(kBlock) void k_fused(KWs ws, KOpts o, const float *targets, float *images,
                                                   int n_views, const uint32_t *order) {
@@ -527,9 +533,10 @@ __global__ __launch_bounds__(kBlock) void k_fused(KWs ws, KOpts o, const float *
   __shared__ ViewInfo s_views[GSR_MAX_VIEWS];
   for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_views[v] = ws.views[v];
   float *hist = ws.history;
+  const int cls = (int)(blockIdx.x & 7u);
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(&ws.hdr->queue, 1u);
+    if (threadIdx.x == 0) s_item = cls + 8 * (int64_t)atomicAdd(&ws.hdr->queue[cls][0], 1u);
     __syncthreads();
     const int64_t item = s_item;
     if (item >= ws.tiles_total) break;
@@ -698,7 +705,8 @@ int launch_raster_bwd(const KWs &ws, const KOpts &o, int64_t tile_lo, int64_t ti
 
 int launch_fused(const KWs &ws, const KOpts &o, const float *targets, float *images, int n_views, int use_history,
                  int lds_batch, int red, int grid_blocks, void *stream) {
-  const dim3 grid((unsigned)grid_blocks), block(kBlock);
+  // a multiple of 8: every workgroup class of the per-XCD counters is present
+  const dim3 grid((unsigned)xcd_grid(grid_blocks > 8 ? grid_blocks : 8)), block(kBlock);
   hipStream_t s = (hipStream_t)stream;
   const uint32_t *order = ws.tile_order;
   const bool hist = use_history != 0;
