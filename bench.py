@@ -130,6 +130,7 @@ def main():
     ap.add_argument("--lds-batch", type=int, default=256, help="with --no-autotune")
     ap.add_argument("--grid-per-cu", type=int, default=8, help="with --no-autotune")
     ap.add_argument("--bwd-reduce", type=int, default=0, help="with --no-autotune")
+    ap.add_argument("--project-table", type=int, default=0, choices=[0, 1], help="with --no-autotune")
     ap.add_argument("--order", choices=["morton", "random"], default="morton",
                     help="storage order of the Gaussians: Morton order of their means (the layout the framework "
                          "keeps), or the generator's random order")
@@ -182,7 +183,8 @@ def main():
     scene_bytes = sum(t.numel() * t.element_size() for t in params.values()) + cams.numel() * 4 + targets.numel() * 4
     torch.cuda.reset_peak_memory_stats()
     rb = Rasterizer(scene.n, scene.sh_degree, sizes, mode="batched", tile=tile, profile_stages=1,
-                    lds_batch=args.lds_batch, grid_per_cu=args.grid_per_cu, bwd_reduce=args.bwd_reduce)
+                    lds_batch=args.lds_batch, grid_per_cu=args.grid_per_cu, bwd_reduce=args.bwd_reduce,
+                    project_table=args.project_table)
     rb.step_l1(params, cams, targets, stats=True)
     counts = rb.counts()
     log(f"visible {counts.visible_total}, union {counts.visible_union}, intersections "
@@ -190,7 +192,8 @@ def main():
     if not args.no_autotune:
         best, ms = rb.autotune(params, cams, targets, reps=2)
         log(f"autotune: tile {best.tile_w}x{best.tile_h}, lds_batch {best.lds_batch}, grid/CU "
-            f"{best.grid_per_cu}, bwd {best.bwd_variant}, reduction {best.bwd_reduce}: {ms:.3f} ms")
+            f"{best.grid_per_cu}, bwd {best.bwd_variant}, reduction {best.bwd_reduce}, project table "
+            f"{best.project_table}: {ms:.3f} ms")
     opt = rb.options
 
     # ---- timed region: K replays of the captured batched step
@@ -262,7 +265,8 @@ def main():
     # ---- plain per-view launches
     ms_plain = None
     if not args.no_plain:
-        rp = Rasterizer(scene.n, scene.sh_degree, sizes, mode="plain", tile=(16, 16))
+        rp = Rasterizer(scene.n, scene.sh_degree, sizes, mode="plain", tile=(16, 16),
+                        project_table=opt.project_table)
         rp.step_l1(params, cams, targets, stats=True)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
@@ -278,7 +282,8 @@ def main():
     if args.order == "morton" and not args.no_plain:
         pr = scene_tensors(scene_random)
         rr = Rasterizer(scene.n, scene.sh_degree, sizes, mode="batched", tile=(opt.tile_w, opt.tile_h),
-                        lds_batch=opt.lds_batch, grid_per_cu=opt.grid_per_cu, bwd_reduce=opt.bwd_reduce)
+                        lds_batch=opt.lds_batch, grid_per_cu=opt.grid_per_cu, bwd_reduce=opt.bwd_reduce,
+                        project_table=opt.project_table)
         with torch.cuda.stream(stream):
             rr.capture(pr, cams, targets, stats=True)
         stream.synchronize()
@@ -598,7 +603,7 @@ def main():
                    "form": "batched fused fwd+L1+bwd with SD statistics, one HIP graph",
                    "tile": f"{opt.tile_w}x{opt.tile_h}", "lds_batch": opt.lds_batch,
                    "grid_per_cu": opt.grid_per_cu, "bwd_variant": "stored" if counts.bwd_variant == 2 else "recompute",
-                   "bwd_reduce": opt.bwd_reduce,
+                   "bwd_reduce": opt.bwd_reduce, "project_table": opt.project_table,
                    "gaussian_order": args.order},
         "gaussians_per_s": round(n * V / (ms_batched * 1e-3), 1),
         "visible_gaussian_views_per_s": round(vis / (ms_batched * 1e-3), 1),

@@ -102,6 +102,10 @@ typedef struct gsr_options {
                              component); 2 = as 1 after DPP sums over lane quads; 3 = as 1 after
                              DPP sums over 16-lane rows, one LDS atomic instruction per entry;
                              4 = as 3 with a reduce-scatter over the rows */
+  int32_t project_table;  /* projection's tile counting: 0 = per-wavefront grouping of lanes that
+                             share a tile, then device atomics; 1 = a per-workgroup table of tiles
+                             in LDS, one device atomic per (workgroup, tile) (pays where wide
+                             footprints make the device atomics' throughput the limit) */
   float near_plane, far_plane;
   float eps2d;           /* low-pass dilation of the 2D covariance */
   float sigma_extent;    /* footprint radius in standard deviations */
@@ -266,13 +270,13 @@ gsr_status gsr_query_counts(gsr_plan *plan, const void *ws, gsr_counts *counts, 
 
 /* Times the batched fused step for each candidate (tile shape 16x16, 32x8,
  * 8x32; lds_batch; grid_per_cu; backward variant within the history budget;
- * reverse reduction 0, 2, 3) with device events, `reps` steps each after one
- * warm-up step, a candidate scoring its fastest step; the three fastest are
- * timed again over 2 reps + 3 steps and the fastest of those is stored in
- * the plan.  Steps write images, loss and grads like
- * gsr_forward_backward_l1.  *best receives the choice (fields
- * tile_w/tile_h/bwd_variant/lds_batch/grid_per_cu/bwd_reduce); best_ms the
- * time of one step (may be NULL). */
+ * reverse reduction 0, 2, 3, 4) with device events, `reps` steps each after
+ * one warm-up step, a candidate scoring its fastest step; the three fastest
+ * are timed again over 2 reps + 3 steps, then the fastest of those with the
+ * other project_table setting; the fastest is stored in the plan.  Steps
+ * write images, loss and grads like gsr_forward_backward_l1.  *best receives
+ * the choice (fields tile_w/tile_h/bwd_variant/lds_batch/grid_per_cu/
+ * bwd_reduce/project_table); best_ms the time of one step (may be NULL). */
 gsr_status gsr_autotune(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera *cams,
                         const float *targets, float *images, float *loss, const gsr_grads *grads,
                         void *ws, size_t ws_bytes, int32_t reps, gsr_options *best,
@@ -294,7 +298,7 @@ gsr_status gsr_last_stage_times(gsr_plan *plan, gsr_stage_times *out);
 /* Current options of a plan (after autotuning). */
 gsr_status gsr_plan_options(const gsr_plan *plan, gsr_options *opt);
 /* Changes the tuning fields (tile_w, tile_h, bwd_variant, lds_batch,
- * grid_per_cu) of a plan; drops a captured graph. */
+ * grid_per_cu, bwd_reduce, project_table) of a plan; drops a captured graph. */
 gsr_status gsr_plan_set_tuning(gsr_plan *plan, const gsr_options *opt);
 
 /* ---- Fast camera selection (Sec. 3.2) -----------------------------------

@@ -115,6 +115,7 @@ gsr_status validate_options(const gsr_options &o) {
   if (o.lds_batch != 64 && o.lds_batch != 128 && o.lds_batch != 256) return GSR_ERR_INVALID_ARG;
   if (o.grid_per_cu < 1 || o.grid_per_cu > 32) return GSR_ERR_INVALID_ARG;
   if (o.bwd_reduce < 0 || o.bwd_reduce > 4) return GSR_ERR_INVALID_ARG;
+  if (o.project_table != 0 && o.project_table != 1) return GSR_ERR_INVALID_ARG;
   if (!(o.near_plane > 0.0f) || !(o.far_plane > o.near_plane)) return GSR_ERR_INVALID_ARG;
   if (!(o.eps2d >= 0.0f) || !(o.sigma_extent > 0.0f) || !(o.jac_clamp > 0.0f)) return GSR_ERR_INVALID_ARG;
   if (!(o.alpha_min > 0.0f) || !(o.alpha_max > o.alpha_min) || !(o.alpha_max < 1.0f)) return GSR_ERR_INVALID_ARG;
@@ -335,7 +336,7 @@ gsr_status enqueue_front(gsr_plan *plan, const gsr_gaussians *g, const gsr_camer
   STAGE(launch_setup(tbl, ws, 0, ws.tiles_total, plan->opt.mode == GSR_MODE_PLAIN ? 1 : 0, plan->prob.n, stream),
          "setup");
   if (plan->opt.mode == GSR_MODE_BATCHED) {
-    STAGE(launch_project(kp, cams, ko, ws, 0, V, 0, stream), "project");
+    STAGE(launch_project(kp, cams, ko, ws, 0, V, 0, plan->opt.project_table, stream), "project");
     STAGE(launch_scan(ws, 0, ws.tiles_total, 0, 0, V, stream), "scan");
     STAGE(launch_emit(ws, plan->prob.n, V, -1, stream), "emit");
     STAGE(launch_sort(ws, 0, ws.tiles_total, stream), "sort");
@@ -345,7 +346,7 @@ gsr_status enqueue_front(gsr_plan *plan, const gsr_gaussians *g, const gsr_camer
   for (int v = 0; v < V; v++) {
     const ViewInfo &vi = tbl.v[v];
     const int64_t nt = (int64_t)vi.tiles_x * vi.tiles_y;
-    STAGE(launch_project(kp, cams, ko, ws, v, v + 1, 1, stream), "project");
+    STAGE(launch_project(kp, cams, ko, ws, v, v + 1, 1, plan->opt.project_table, stream), "project");
     STAGE(launch_scan(ws, vi.tile_base, vi.tile_base + nt, base, v, v + 1, stream), "scan");
     uint32_t iv = 0;
     HIPCHK(hipMemcpyAsync(&iv, &ws.hdr->isect[v], sizeof iv, hipMemcpyDeviceToHost, (hipStream_t)stream), "count read-back");
@@ -399,7 +400,7 @@ gsr_status enqueue_plain_l1(gsr_plan *plan, const gsr_gaussians *g, const gsr_ca
   for (int v = 0; v < V; v++) {
     const ViewInfo &vi = tbl.v[v];
     const int64_t nt = (int64_t)vi.tiles_x * vi.tiles_y;
-    STAGE(launch_project(kp, cams, ko, ws, v, v + 1, 1, stream), "project");
+    STAGE(launch_project(kp, cams, ko, ws, v, v + 1, 1, plan->opt.project_table, stream), "project");
     STAGE(launch_scan(ws, vi.tile_base, vi.tile_base + nt, base, v, v + 1, stream), "scan");
     uint32_t iv = 0;
     HIPCHK(hipMemcpyAsync(&iv, &ws.hdr->isect[v], sizeof iv, hipMemcpyDeviceToHost, (hipStream_t)stream), "count read-back");
@@ -444,6 +445,7 @@ void gsr_default_options(gsr_options *o) {
   o->lds_batch = 128;
   o->grid_per_cu = 4;
   o->bwd_reduce = 0;
+  o->project_table = 0;
   o->accumulate_grads = 0;
   o->check_finite = 0;
   o->near_plane = 0.01f;
@@ -529,6 +531,7 @@ gsr_status gsr_plan_set_tuning(gsr_plan *plan, const gsr_options *t) {
   o.lds_batch = t->lds_batch;
   o.grid_per_cu = t->grid_per_cu;
   o.bwd_reduce = t->bwd_reduce;
+  o.project_table = t->project_table;
   if (validate_options(o) != GSR_OK) return GSR_ERR_INVALID_ARG;
   const size_t old_bytes = plan->ws_bytes;
   const int64_t old_hist = plan->layout.history_entries;
@@ -843,6 +846,17 @@ gsr_status gsr_autotune(gsr_plan *plan, const gsr_gaussians *g, const gsr_camera
     if (s == GSR_OK && ms < best_t) {
       best_t = ms;
       best_o = timed[c].second;
+    }
+  }
+  // the projection's tile counting, on the chosen raster tuning
+  if (s == GSR_OK && best_t < 1e29f) {
+    gsr_options alt = best_o;
+    alt.project_table = 1 - best_o.project_table;
+    float ms = 0.f;
+    s = time_candidate(alt, 2 * reps + 3, ms);
+    if (s == GSR_OK && ms < best_t) {
+      best_t = ms;
+      best_o = alt;
     }
   }
   plan->capturing = false;

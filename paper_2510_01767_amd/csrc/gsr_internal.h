@@ -113,7 +113,7 @@ int launch_setup(const ViewTable &table, const KWs &ws, int64_t zero_tiles_from,
 int launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, void *stream);
 int launch_fill_f32(float *p, float value, int64_t count, void *stream);
 int launch_project(const KParams &p, const gsr_camera *cams, const KOpts &o, const KWs &ws, int view_lo,
-                   int view_hi, int or_bits, void *stream);
+                   int view_hi, int or_bits, int table, void *stream);
 int launch_scan(const KWs &ws, int64_t tile_lo, int64_t tile_hi, int64_t base, int view_lo, int view_hi,
                 void *stream);
 int launch_emit(const KWs &ws, int64_t n, int n_views, int view_only, void *stream);

@@ -70,13 +70,49 @@ __device__ __forceinline__ bool finite_params(const KParams &p, int64_t i) {
   return acc == 0.0f;  // any Inf or NaN makes the product NaN
 }
 
-template <int D>
+// With TABLE, a workgroup's table of the tiles its records touch, in LDS:
+// open addressing on the tile id, linear probing.  cnt counts the ranked
+// entries (the LDS atomic's return value is the rank within the workgroup),
+// fill the overflow ones; base receives the workgroup's start in the tile's
+// bucket.
+constexpr int kTileTable = 1024, kTileProbes = 16;
+constexpr uint32_t kNoTile = 0xffffffffu;
+
+template <int N>
+struct TileTable {
+  uint32_t key[N], cnt[N], fill[N], base[N];
+};
+
+// The table slot of tile t, inserting it if absent; -1 when the probe
+// sequence is full.
+__device__ __forceinline__ int tile_table_slot(TileTable<kTileTable> &tt, uint32_t t) {
+  const uint32_t h = (t * 2654435761u) >> 22;  // 10 bits
+  for (int k = 0; k < kTileProbes; k++) {
+    const int e = (int)((h + (uint32_t)k) & (uint32_t)(kTileTable - 1));
+    const uint32_t cur = *reinterpret_cast<volatile uint32_t *>(&tt.key[e]);
+    if (cur == t) return e;
+    if (cur == kNoTile) {
+      const uint32_t prev = atomicCAS(&tt.key[e], kNoTile, t);
+      if (prev == kNoTile || prev == t) return e;
+    }
+  }
+  return -1;
+}
+
+template <int D, bool TABLE>
 __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera *cams, KOpts o, KWs ws,
                                                     int view_lo, int view_hi, int or_bits) {
   constexpr int K = (D + 1) * (D + 1);
   __shared__ Cam64 s_cam[GSR_MAX_VIEWS];
   __shared__ ViewInfo s_view[GSR_MAX_VIEWS];
+  __shared__ TileTable<TABLE ? kTileTable : 1> s_tt;
   for (int v = threadIdx.x; v < p.n_views; v += blockDim.x) s_view[v] = ws.views[v];
+  if (TABLE)
+    for (int e = threadIdx.x; e < kTileTable; e += blockDim.x) {
+      s_tt.key[e] = kNoTile;
+      s_tt.cnt[e] = 0u;
+      s_tt.fill[e] = 0u;
+    }
   load_cams(s_cam, cams, ws.views, p.n_views, o);
   const int64_t n = p.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -104,7 +140,8 @@ __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera 
     Proj P;
     // the exact projection only where the conservative bound leaves a chance
     const bool vis = keep && maybe_visible(g, cam, o) && project_view(g, cam, o, P);
-    if (__ballot(vis) == 0ull) continue;  // (the whole wavefront stays in the loop)
+    // (the whole wavefront, with TABLE the whole workgroup, stays in the loop)
+    if (TABLE ? !__syncthreads_or(vis) : __ballot(vis) == 0ull) continue;
     const int64_t r = (int64_t)v * n + i;
     uint4 r3 = make_uint4(0u, 0u, 0u, 0u);
     int wx = 1, ntiles = 0;
@@ -126,73 +163,117 @@ __global__ __launch_bounds__(kBlock) void k_project(KParams p, const gsr_camera 
       ntiles = wx * (P.y1 - P.y0 + 1);
     }
     // Count the record into each tile it touches.  For the first four tiles
-    // (row-major) the count atomic's return value is the record's rank in
-    // that tile's bucket, kept so that the scatter needs no atomics; further
-    // tiles (large footprints, rare) are counted apart and placed after the
-    // ranked ones.  When the wavefront's records sit close together on the
-    // tile grid (Gaussians stored in spatial order), lanes that share a tile
-    // take one atomic for all of them, ranked by lane within it; otherwise,
-    // and for what a few rounds leave, one atomic per (record, tile).
+    // (row-major) the record's rank in the tile's bucket comes out of the
+    // count, kept so that the scatter needs no atomics; further tiles (large
+    // footprints) are counted apart and placed after the ranked ones.
     const int x0 = P.x0, y0 = P.y0;
     auto tile_q = [&](int q) -> int32_t {
       const int dy = q / wx, dx = q - dy * wx;
       return (int32_t)(vi.tile_base + (int64_t)(y0 + dy) * vi.tiles_x + (x0 + dx));
     };
-    const int32_t t0 = vis ? tile_q(0) : 0;
-    int32_t tmin = vis ? t0 : INT32_MAX, tmax = vis ? t0 : -1;
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-      tmin = min(tmin, __shfl_xor(tmin, m));
-      tmax = max(tmax, __shfl_xor(tmax, m));
-    }
-    const bool gather = tmax - tmin <= 2 * vi.tiles_x + 2;
-    // Group the lanes that share a tile (per rank slot q) with ballots only:
-    // which group no atomic result decides, so the groups are formed first,
-    // each group's lowest lane then takes one atomic for the group, and all
-    // of a lane's atomics are in flight together.  Lanes left after the
-    // rounds, or all lanes when the wavefront is spread out, form groups of
-    // one.
-    int32_t tq[4];
-    bool pending[4];
-    int ldr[4];
-    uint32_t off[4], cnt[4];
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      tq[q] = q < ntiles ? tile_q(q) : -1;
-      pending[q] = tq[q] >= 0;
-      ldr[q] = lane;
-      off[q] = 0u;
-      cnt[q] = 0u;
-    }
-    for (int round = 0; gather && round < 8; round++) {
-      bool any = false;
+    uint32_t rk[4];
+    if constexpr (TABLE) {
+      // The workgroup counts into its table first (the rank within the
+      // workgroup from the LDS atomic), then takes one device atomic per
+      // distinct tile for all of it; a tile the table cannot hold takes
+      // device atomics directly.  For wide footprints (many tiles per record,
+      // many records per tile) the device atomics' throughput is what limits
+      // this kernel, and the table divides their number.
+      int slot[4];
 #pragma unroll
       for (int q = 0; q < 4; q++) {
-        const uint64_t act = __ballot(pending[q]);
-        if (act == 0ull) continue;
-        any = true;
-        const int L = __ffsll((unsigned long long)act) - 1;
-        const int32_t lt = __shfl(tq[q], L);
-        const bool same = pending[q] && tq[q] == lt;
-        const uint64_t m = __ballot(same);
-        if (same) {
-          ldr[q] = L;
-          off[q] = (uint32_t)__popcll(m & below);
-          pending[q] = false;
+        slot[q] = -1;
+        rk[q] = 0u;
+        if (q < ntiles) {
+          const int32_t t = tile_q(q);
+          slot[q] = tile_table_slot(s_tt, (uint32_t)t);
+          if (slot[q] >= 0) rk[q] = atomicAdd(&s_tt.cnt[slot[q]], 1u);
+          else rk[q] = atomicAdd(&ws.tile_count[t], 1u);
         }
-        if (lane == L) cnt[q] = (uint32_t)__popcll(m);
       }
-      if (!any) break;
-    }
-    uint32_t base[4], rk[4];
+      for (int q = 4; q < ntiles; q++) {
+        const int32_t t = tile_q(q);
+        const int e = tile_table_slot(s_tt, (uint32_t)t);
+        if (e >= 0) atomicAdd(&s_tt.fill[e], 1u);
+        else atomicAdd(&ws.tile_fill[t], 1u);
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < kTileTable; e += blockDim.x) {
+        const uint32_t t = s_tt.key[e];
+        if (t != kNoTile) {
+          const uint32_t c = s_tt.cnt[e], f = s_tt.fill[e];
+          s_tt.base[e] = c ? atomicAdd(&ws.tile_count[t], c) : 0u;
+          if (f) atomicAdd(&ws.tile_fill[t], f);
+          s_tt.key[e] = kNoTile;
+          s_tt.cnt[e] = 0u;
+          s_tt.fill[e] = 0u;
+        }
+      }
+      __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      if (pending[q]) cnt[q] = 1u;  // a group of one (ldr = lane, off = 0)
-      base[q] = cnt[q] ? atomicAdd(&ws.tile_count[tq[q]], cnt[q]) : 0u;
+      for (int q = 0; q < 4; q++)
+        if (slot[q] >= 0) rk[q] += s_tt.base[slot[q]];
+    } else {
+      // When the wavefront's records sit close together on the tile grid
+      // (Gaussians stored in spatial order), lanes that share a tile take one
+      // atomic for all of them, ranked by lane within it; otherwise, and for
+      // what a few rounds leave, one atomic per (record, tile).
+      const int32_t t0 = vis ? tile_q(0) : 0;
+      int32_t tmin = vis ? t0 : INT32_MAX, tmax = vis ? t0 : -1;
+  #pragma unroll
+      for (int m = 1; m < 64; m <<= 1) {
+        tmin = min(tmin, __shfl_xor(tmin, m));
+        tmax = max(tmax, __shfl_xor(tmax, m));
+      }
+      const bool gather = tmax - tmin <= 2 * vi.tiles_x + 2;
+      // Group the lanes that share a tile (per rank slot q) with ballots only:
+      // which group no atomic result decides, so the groups are formed first,
+      // each group's lowest lane then takes one atomic for the group, and all
+      // of a lane's atomics are in flight together.  Lanes left after the
+      // rounds, or all lanes when the wavefront is spread out, form groups of
+      // one.
+      int32_t tq[4];
+      bool pending[4];
+      int ldr[4];
+      uint32_t off[4], cnt[4];
+  #pragma unroll
+      for (int q = 0; q < 4; q++) {
+        tq[q] = q < ntiles ? tile_q(q) : -1;
+        pending[q] = tq[q] >= 0;
+        ldr[q] = lane;
+        off[q] = 0u;
+        cnt[q] = 0u;
+      }
+      for (int round = 0; gather && round < 8; round++) {
+        bool any = false;
+  #pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const uint64_t act = __ballot(pending[q]);
+          if (act == 0ull) continue;
+          any = true;
+          const int L = __ffsll((unsigned long long)act) - 1;
+          const int32_t lt = __shfl(tq[q], L);
+          const bool same = pending[q] && tq[q] == lt;
+          const uint64_t m = __ballot(same);
+          if (same) {
+            ldr[q] = L;
+            off[q] = (uint32_t)__popcll(m & below);
+            pending[q] = false;
+          }
+          if (lane == L) cnt[q] = (uint32_t)__popcll(m);
+        }
+        if (!any) break;
+      }
+      uint32_t base[4];
+  #pragma unroll
+      for (int q = 0; q < 4; q++) {
+        if (pending[q]) cnt[q] = 1u;  // a group of one (ldr = lane, off = 0)
+        base[q] = cnt[q] ? atomicAdd(&ws.tile_count[tq[q]], cnt[q]) : 0u;
+      }
+  #pragma unroll
+      for (int q = 0; q < 4; q++) rk[q] = __shfl(base[q], ldr[q]) + off[q];
+      for (int q = 4; q < ntiles; q++) atomicAdd(&ws.tile_fill[tile_q(q)], 1u);
     }
-#pragma unroll
-    for (int q = 0; q < 4; q++) rk[q] = __shfl(base[q], ldr[q]) + off[q];
-    for (int q = 4; q < ntiles; q++) atomicAdd(&ws.tile_fill[tile_q(q)], 1u);
     if (vis) {
       // the record's slot in one 64-byte write: cleared gradient, ranks, rectangle, depth
       uint4 *sl = reinterpret_cast<uint4 *>(ws.grad2d + r * kGrad2dStride);
@@ -991,15 +1072,21 @@ int launch_fill_f32(float *p, float value, int64_t count, void *stream) {
 }
 
 int launch_project(const KParams &p, const gsr_camera *cams, const KOpts &o, const KWs &ws, int view_lo,
-                   int view_hi, int or_bits, void *stream) {
+                   int view_hi, int or_bits, int table, void *stream) {
   const dim3 grid(grid_for(p.n)), block(kBlock);
   hipStream_t s = (hipStream_t)stream;
+#define GSR_PROJECT(D_)                                                                                        \
+  do {                                                                                                        \
+    if (table) hipLaunchKernelGGL((k_project<D_, true>), grid, block, 0, s, p, cams, o, ws, view_lo, view_hi, or_bits); \
+    else hipLaunchKernelGGL((k_project<D_, false>), grid, block, 0, s, p, cams, o, ws, view_lo, view_hi, or_bits);      \
+  } while (0)
   switch (p.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project<0>, grid, block, 0, s, p, cams, o, ws, view_lo, view_hi, or_bits); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, grid, block, 0, s, p, cams, o, ws, view_lo, view_hi, or_bits); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, s, p, cams, o, ws, view_lo, view_hi, or_bits); break;
-    default: hipLaunchKernelGGL(k_project<3>, grid, block, 0, s, p, cams, o, ws, view_lo, view_hi, or_bits); break;
+    case 0: GSR_PROJECT(0); break;
+    case 1: GSR_PROJECT(1); break;
+    case 2: GSR_PROJECT(2); break;
+    default: GSR_PROJECT(3); break;
   }
+#undef GSR_PROJECT
   return last_err();
 }
 

@@ -45,7 +45,7 @@ class gsr_options(ctypes.Structure):
     _fields_ = [
         ("mode", _i32), ("tile_w", _i32), ("tile_h", _i32), ("bwd_variant", _i32),
         ("lds_batch", _i32), ("grid_per_cu", _i32), ("accumulate_grads", _i32), ("check_finite", _i32),
-        ("profile_stages", _i32), ("bwd_reduce", _i32), ("near_plane", _f32), ("far_plane", _f32), ("eps2d", _f32), ("sigma_extent", _f32),
+        ("profile_stages", _i32), ("bwd_reduce", _i32), ("project_table", _i32), ("near_plane", _f32), ("far_plane", _f32), ("eps2d", _f32), ("sigma_extent", _f32),
         ("jac_clamp", _f32), ("alpha_min", _f32), ("alpha_max", _f32), ("T_min", _f32),
         ("bg", _f32 * 3), ("stat_scale", _f32),
         ("capacity_intersections", _i64), ("history_budget_bytes", _i64),

@@ -16,7 +16,7 @@ static int no_device() { return (int)hipErrorNoDevice; }
 int launch_setup(const ViewTable &, const KWs &, int64_t, int64_t, int, int64_t, void *) { return no_device(); }
 int launch_fill_u32(uint32_t *, uint32_t, int64_t, void *) { return no_device(); }
 int launch_fill_f32(float *, float, int64_t, void *) { return no_device(); }
-int launch_project(const KParams &, const gsr_camera *, const KOpts &, const KWs &, int, int, int, void *) {
+int launch_project(const KParams &, const gsr_camera *, const KOpts &, const KWs &, int, int, int, int, void *) {
   return no_device();
 }
 int launch_scan(const KWs &, int64_t, int64_t, int64_t, int, int, void *) { return no_device(); }

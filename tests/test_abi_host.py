@@ -29,7 +29,7 @@ def test_every_declared_function_is_exported():
 
 def test_struct_sizes_match_the_header():
     assert ctypes.sizeof(C.gsr_camera) == 64
-    assert ctypes.sizeof(C.gsr_options) == 4 * 10 + 4 * 12 + 8 * 2
+    assert ctypes.sizeof(C.gsr_options) == 4 * 11 + 4 * 12 + 4 + 8 * 2  # 4 bytes of padding before the int64s
     assert ctypes.sizeof(C.gsr_stage_times) == 4 + 16 * 4 + 16 * 4 + 16 * 32
 
 
@@ -70,6 +70,7 @@ def test_defaults():
     lambda p, o: setattr(o, "grid_per_cu", 0),
     lambda p, o: setattr(o, "mode", 7),
     lambda p, o: setattr(o, "bwd_reduce", 5),
+    lambda p, o: setattr(o, "project_table", 2),
     lambda p, o: setattr(o, "alpha_max", 1.0),
     lambda p, o: setattr(o, "T_min", 0.0),
     lambda p, o: setattr(o, "near_plane", -1.0),

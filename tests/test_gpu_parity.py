@@ -86,11 +86,12 @@ def test_config0_step_matches_oracle(c0, mode):
     print("report", rep)
 
 
+@pytest.mark.parametrize("project_table", [0, 1])
 @pytest.mark.parametrize("scene_name", ["config0", "ragged"])
-def test_records_and_binning_bit_exact(scene_name, c0, ragged):
+def test_records_and_binning_bit_exact(scene_name, project_table, c0, ragged):
     scene = c0 if scene_name == "config0" else ragged
-    announce("records/binning", scene_name)
-    r, params, cams, targets, _ = run_step(scene, mode="batched")
+    announce("records/binning", scene_name, "project table", project_table)
+    r, params, cams, targets, _ = run_step(scene, mode="batched", project_table=project_table)
     ora = ora_step(scene)
     n, V = scene.n, scene.n_views
     L = r.layout
@@ -241,9 +242,11 @@ def test_forward_backward_split_equals_fused_l1(ragged):
     d = d * torch.cat(scales)
     r2.backward(params, cams, d.contiguous())
     torch.cuda.synchronize()
+    # the same arithmetic; only the order of the float32 atomic sums differs
+    # (as between the stored and recomputed reverse passes)
     for k in rf.grads:
         a, b = r2.grads[k].cpu().numpy(), rf.grads[k].cpu().numpy()
-        assert np.linalg.norm(a - b) <= 1e-6 * max(np.linalg.norm(b), 1e-30), k
+        assert np.linalg.norm(a - b) <= 1e-5 * max(np.linalg.norm(b), 1e-30), k
 
 
 def test_visibility_mask_matches_oracle(ragged):
