@@ -527,12 +527,14 @@ __global__ __launch_bounds__(kBlock) void k_emit(KWs ws, int64_t n, int n_views,
 // bitonic network: partners closer than R sit in the same lane, the others
 // in lane ^ (j / R), reached by DPP moves for lane distances 1, 2, 4, 8 and
 // by shuffles for 16 and 32.  No LDS traffic besides those shuffles, no
-// barrier.  Larger tiles: one workgroup per tile, LDS bitonic sort of up to
-// kSortLds keys, merge passes in global memory beyond that.
+// barrier.  Longer tiles are cut into runs of kRun keys; a workgroup sorts a
+// run with its four wavefronts (1024 keys each, in registers as above) and
+// two merge levels in LDS.  Tiles longer than one run are then merged run by
+// run in global memory.
 
-constexpr int kWaveSortMax = 4096;  // 64 lanes x 64 keys
+constexpr int kWaveSortMax = 2048;  // 64 lanes x 32 keys
 constexpr int kSortBigThreads = 1024;
-constexpr int kSortLds = 4096;
+constexpr int kRun = 4096;          // four wavefronts x 1024 keys
 
 template <int CTRL>
 __device__ __forceinline__ uint64_t dpp_u64(uint64_t x) {
@@ -644,30 +646,6 @@ __global__ __launch_bounds__(kBlock) void k_sort_wave(KWs ws, int64_t tile_lo, i
   else wave_sort_tile<(RMAX >= 16 ? 16 : 8)>(keys, n);
 }
 
-__device__ void bitonic_lds(uint64_t *s, int n2) {
-  for (int k = 2; k <= n2; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const uint64_t a = s[i], b = s[ixj];
-          const bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            s[i] = b;
-            s[ixj] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-}
-
-__device__ __forceinline__ int next_pow2(int x) {
-  int p = 1;
-  while (p < x) p <<= 1;
-  return p;
-}
-
 // Merge two sorted runs A[0, la), B[0, lb) into out.  Each thread takes a
 // contiguous chunk of kMergeChunk outputs: one co-rank binary search finds
 // where the chunk starts in A and in B (keys are unique), then the chunk is
@@ -692,22 +670,13 @@ __device__ void merge_runs(const uint64_t *A, int64_t la, const uint64_t *B, int
   }
 }
 
-// One workgroup sorts one tile of more than kWaveSortMax entries.
-__device__ void sort_tile_block(const KWs &ws, int64_t t, uint64_t *s) {
+// One workgroup merges the sorted runs of one tile of more than kRun entries.
+__device__ void merge_tile_block(const KWs &ws, int64_t t) {
   const int64_t start = ws.tile_start[t];
   const int64_t n = (int64_t)ws.tile_start[t + 1] - start;
   uint64_t *keys = ws.keys + start;
-  for (int64_t c0 = 0; c0 < n; c0 += kSortLds) {
-    const int m = (int)min((int64_t)kSortLds, n - c0);
-    const int n2 = next_pow2(m);
-    for (int k = threadIdx.x; k < n2; k += blockDim.x) s[k] = k < m ? keys[c0 + k] : ~0ull;
-    __syncthreads();
-    bitonic_lds(s, n2);
-    for (int k = threadIdx.x; k < m; k += blockDim.x) keys[c0 + k] = s[k];
-    __syncthreads();
-  }
   uint64_t *src = keys, *dst = ws.keys_alt + start;
-  for (int64_t w = kSortLds; w < n; w <<= 1) {
+  for (int64_t w = kRun; w < n; w <<= 1) {
     for (int64_t a = 0; a < n; a += 2 * w) {
       const int64_t la = min(w, n - a);
       const int64_t lb = min(w, max((int64_t)0, n - a - w));
@@ -724,30 +693,110 @@ __device__ void sort_tile_block(const KWs &ws, int64_t t, uint64_t *s) {
   __syncthreads();
 }
 
-// Each workgroup checks kSortBigThreads tiles at once (one per thread),
-// lists the large ones in LDS and sorts them one after the other (the list
-// and its length are uniform per workgroup, so every thread reaches every
-// barrier).  Tiles this large are rare (dense spots of a view).
-// Tiles longer than one wavefront's register sort: collected into a list
-// (tile_order is free between the scan and the schedule), then sorted by
-// persistent 1024-thread workgroups that take them one at a time, so long
-// tiles spread over the whole chip.
+// Runs of the tiles longer than one wavefront's register sort, listed per
+// sort call (tile, run index) in keys_alt, which the merge passes use only
+// after the runs are sorted; the tiles longer than one run in tile_order
+// (free between the scan and the schedule).  Workgroups take runs, then
+// tiles, from counters, so long tiles spread over the whole chip.
 __global__ void k_big_reset(KWs ws) {
   ws.hdr->big_count = 0u;
   ws.hdr->big_next = 0u;
+  ws.hdr->run_count = 0u;
+  ws.hdr->run_next = 0u;
 }
+
+__device__ __forceinline__ uint32_t *run_list(const KWs &ws) { return reinterpret_cast<uint32_t *>(ws.keys_alt); }
 
 __global__ __launch_bounds__(kBlock) void k_big_collect(KWs ws, int64_t tile_lo, int64_t tile_count) {
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < tile_count;
        b += (int64_t)gridDim.x * blockDim.x) {
     const int64_t t = tile_lo + b;
-    if ((int64_t)ws.tile_start[t + 1] - ws.tile_start[t] > kWaveSortMax)
-      ws.tile_order[atomicAdd(&ws.hdr->big_count, 1u)] = (uint32_t)t;
+    const int64_t n = (int64_t)ws.tile_start[t + 1] - ws.tile_start[t];
+    if (n <= kWaveSortMax) continue;
+    const uint32_t runs = (uint32_t)((n + kRun - 1) / kRun);
+    const uint32_t at = atomicAdd(&ws.hdr->run_count, runs);
+    uint32_t *list = run_list(ws);
+    for (uint32_t c = 0; c < runs; c++) {
+      list[2 * (at + c)] = (uint32_t)t;
+      list[2 * (at + c) + 1] = c;
+    }
+    if (n > kRun) ws.tile_order[atomicAdd(&ws.hdr->big_count, 1u)] = (uint32_t)t;
   }
 }
 
+// One level of merges inside a run in LDS: the sorted blocks of w keys are
+// merged in pairs into blocks of 2w.  Each thread produces kRun / kBlock
+// consecutive outputs after one co-rank search (keys are unique), holds them
+// in registers over a barrier and stores them in place.
+__device__ __forceinline__ void merge_level_lds(uint64_t *s, int w) {
+  constexpr int kPer = kRun / kBlock;
+  const int o0 = (int)threadIdx.x * kPer;
+  const int pair = o0 / (2 * w), k0 = o0 - pair * 2 * w;
+  const uint64_t *A = s + pair * 2 * w, *B = A + w;
+  int lo = k0 > w ? k0 - w : 0, hi = k0 < w ? k0 : w;
+  while (lo < hi) {
+    const int ia = (lo + hi) >> 1;
+    if (A[ia] < B[k0 - ia - 1]) lo = ia + 1;
+    else hi = ia;
+  }
+  int ia = lo, ib = k0 - lo;
+  uint64_t out[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; k++) {
+    const uint64_t a = A[min(ia, w - 1)], b = B[min(ib, w - 1)];  // (reads stay inside the pair)
+    const bool takeA = ib >= w || (ia < w && a < b);
+    out[k] = takeA ? a : b;
+    ia += takeA ? 1 : 0;
+    ib += takeA ? 0 : 1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; k++) s[o0 + k] = out[k];
+  __syncthreads();
+}
+
+// Sorts the listed runs: each wavefront sorts its quarter of the run in
+// registers, then two merge levels in LDS give the sorted run.  Missing
+// keys of a short run are padded with distinct values above every key,
+// ascending with the position (depth bits of a finite float stay below
+// 0x7f800000 in the high word), so a quarter of padding only is sorted.
+__global__ __launch_bounds__(kBlock) void k_sort_runs(KWs ws) {
+  constexpr int kQuarter = kRun / 4, R = kQuarter / 64;
+  __shared__ uint64_t s[kRun];
+  __shared__ uint32_t s_k;
+  const uint32_t count = ws.hdr->run_count;
+  const uint32_t *list = run_list(ws);
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  for (;;) {
+    if (threadIdx.x == 0) s_k = atomicAdd(&ws.hdr->run_next, 1u);
+    __syncthreads();
+    const uint32_t k = s_k;
+    if (k >= count) break;
+    const int64_t t = list[2 * k];
+    const int64_t c0 = (int64_t)list[2 * k + 1] * kRun;
+    const int64_t start = ws.tile_start[t];
+    const int m = (int)min((int64_t)kRun, (int64_t)ws.tile_start[t + 1] - start - c0);
+    uint64_t *keys = ws.keys + start + c0;
+    const int q0 = wave * kQuarter;
+    uint64_t x[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int e = q0 + lane * R + r;
+      x[r] = e < m ? keys[e] : ~0ull - (uint64_t)(kRun - 1 - e);
+    }
+    if (q0 < m) BitonicSort<R, 1, 10>::run(x, lane);  // (uniform per wavefront)
+#pragma unroll
+    for (int r = 0; r < R; r++) s[q0 + lane * R + r] = x[r];
+    __syncthreads();
+    merge_level_lds(s, kQuarter);
+    merge_level_lds(s, 2 * kQuarter);
+    for (int e = threadIdx.x; e < m; e += kBlock) keys[e] = s[e];
+    __syncthreads();
+  }
+}
+
+// Merges the runs of the tiles longer than one run, one tile per workgroup.
 __global__ __launch_bounds__(kSortBigThreads) void k_sort_big(KWs ws) {
-  __shared__ uint64_t s[kSortLds];
   __shared__ uint32_t s_k;
   const uint32_t count = ws.hdr->big_count;
   for (;;) {
@@ -755,7 +804,7 @@ __global__ __launch_bounds__(kSortBigThreads) void k_sort_big(KWs ws) {
     __syncthreads();
     const uint32_t k = s_k;
     if (k >= count) break;
-    sort_tile_block(ws, ws.tile_order[k], s);  // ends with a barrier, before s_k is written again
+    merge_tile_block(ws, ws.tile_order[k]);  // ends with a barrier, before s_k is written again
   }
 }
 
@@ -1116,10 +1165,10 @@ int launch_sort(const KWs &ws, int64_t tile_lo, int64_t tile_count, void *stream
   const dim3 wgrid((unsigned)xcd_grid((tile_count + 3) / 4));
   hipLaunchKernelGGL(k_sort_wave<16>, wgrid, dim3(kBlock), 0, s, ws, tile_lo, tile_count, 0);
   hipLaunchKernelGGL(k_sort_wave<32>, wgrid, dim3(kBlock), 0, s, ws, tile_lo, tile_count, 1024);
-  hipLaunchKernelGGL(k_sort_wave<64>, wgrid, dim3(kBlock), 0, s, ws, tile_lo, tile_count, 2048);
   hipLaunchKernelGGL(k_big_reset, dim3(1), dim3(1), 0, s, ws);
   hipLaunchKernelGGL(k_big_collect, dim3((unsigned)min((tile_count + kBlock - 1) / kBlock, (int64_t)4096)),
                      dim3(kBlock), 0, s, ws, tile_lo, tile_count);
+  hipLaunchKernelGGL(k_sort_runs, dim3(2048), dim3(kBlock), 0, s, ws);
   hipLaunchKernelGGL(k_sort_big, dim3(512), dim3(kSortBigThreads), 0, s, ws);
   return last_err();
 }

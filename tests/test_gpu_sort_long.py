@@ -5,8 +5,9 @@ of every (view, Gaussian) record, and its visibility bits) are binned and
 ordered by the FP64 oracle's integer binning; the GPU's keys must equal the
 oracle's entry for entry and its tile ranges must be identical.  The scene
 is built so that every length class of the per-tile sort occurs: one
-wavefront in registers up to 1024, 2048 and 4096 entries, and the
-persistent workgroup sort (LDS runs of 4096 plus merge passes) beyond."""
+wavefront in registers up to 1024 and 2048 entries, a workgroup's run sort
+(four wavefronts in registers, then merges in LDS) up to 4096, and runs plus
+merge passes in global memory beyond."""
 import numpy as np
 import pytest
 import torch
@@ -20,20 +21,21 @@ from tests import parity
 pytestmark = pytest.mark.gpu
 
 # length classes of the per-tile sort: (lowest, highest, path)
-CLASSES = ((2, 1024, "k_sort_wave<16>"), (1025, 2048, "k_sort_wave<32>"), (2049, 4096, "k_sort_wave<64>"),
-           (4097, 1 << 31, "k_sort_big"))
+CLASSES = ((2, 1024, "k_sort_wave<16>"), (1025, 2048, "k_sort_wave<32>"), (2049, 4096, "k_sort_runs"),
+           (4097, 1 << 31, "k_sort_runs + k_sort_big"))
 
 
-@pytest.mark.parametrize("tile", [(16, 16), (8, 32)])
-def test_long_tile_binning_and_order_bit_exact(tile):
+@pytest.mark.parametrize("tile,project_table", [((16, 16), 0), ((8, 32), 0), ((16, 16), 1)])
+def test_long_tile_binning_and_order_bit_exact(tile, project_table):
     if not torch.cuda.is_available():
         pytest.fail("GPU tests need a ROCm GPU")
     C.load(build_if_missing=False)
     s = scenes.dense_cloud()
     n, V = s.n, s.n_views
-    print("[gpu-case] long-tile sort", s.name, tile, flush=True)
+    print("[gpu-case] long-tile sort", s.name, tile, "project table", project_table, flush=True)
     sizes = [(c["W"], c["H"]) for c in s.cameras]
-    r = Rasterizer(n, s.sh_degree, sizes, mode="batched", tile=tile, capacity=8_000_000)
+    r = Rasterizer(n, s.sh_degree, sizes, mode="batched", tile=tile, capacity=8_000_000,
+                   project_table=project_table)
     r.forward(scene_tensors(s), camera_tensor(s.cameras))
     torch.cuda.synchronize()
     counts = r.counts()
