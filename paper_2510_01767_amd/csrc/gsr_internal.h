@@ -28,12 +28,14 @@ struct ViewTable {
 struct WsHeader {
   uint32_t overflow;
   uint32_t nonfinite;
-  uint32_t run_count;     // 4096-key runs of long tiles, listed per sort call
+  uint32_t run_count;     // runs of 4096 keys (tiles of 2049..4096 entries), listed per sort call
   uint32_t union_count;   // Gaussians visible in >= 1 view
   uint32_t isect_total;
   uint32_t big_count;     // tiles whose lists exceed one wavefront's sort, collected per sort call
   uint32_t big_next;      // their work counter
-  uint32_t run_next;      // the runs' work counter
+  uint32_t run_next;      // their work counter
+  uint32_t run8_count;    // runs of 8192 keys (the runs of longer tiles)
+  uint32_t run8_next;
   uint32_t isect[GSR_MAX_VIEWS];
   uint32_t visible[GSR_MAX_VIEWS];
   // longest-list-first schedule of the persistent raster: tiles per length

@@ -527,14 +527,15 @@ __global__ __launch_bounds__(kBlock) void k_emit(KWs ws, int64_t n, int n_views,
 // bitonic network: partners closer than R sit in the same lane, the others
 // in lane ^ (j / R), reached by DPP moves for lane distances 1, 2, 4, 8 and
 // by shuffles for 16 and 32.  No LDS traffic besides those shuffles, no
-// barrier.  Longer tiles are cut into runs of kRun keys; a workgroup sorts a
-// run with its four wavefronts (1024 keys each, in registers as above) and
-// two merge levels in LDS.  Tiles longer than one run are then merged run by
-// run in global memory.
+// barrier.  Longer tiles are sorted as runs: tiles of up to 4096 entries as
+// one run of 4096 keys, longer ones cut into runs of 8192; a workgroup sorts
+// a run with four or eight wavefronts (1024 keys each, in registers as above)
+// and two or three merge levels in LDS.  Tiles longer than one run are then
+// merged run by run in global memory.
 
 constexpr int kWaveSortMax = 2048;  // 64 lanes x 32 keys
 constexpr int kSortBigThreads = 1024;
-constexpr int kRun = 4096;          // four wavefronts x 1024 keys
+constexpr int kRunLong = 8192;      // the runs of tiles longer than 4096
 
 template <int CTRL>
 __device__ __forceinline__ uint64_t dpp_u64(uint64_t x) {
@@ -670,13 +671,13 @@ __device__ void merge_runs(const uint64_t *A, int64_t la, const uint64_t *B, int
   }
 }
 
-// One workgroup merges the sorted runs of one tile of more than kRun entries.
+// One workgroup merges the sorted runs of one tile of more than kRunLong entries.
 __device__ void merge_tile_block(const KWs &ws, int64_t t) {
   const int64_t start = ws.tile_start[t];
   const int64_t n = (int64_t)ws.tile_start[t + 1] - start;
   uint64_t *keys = ws.keys + start;
   uint64_t *src = keys, *dst = ws.keys_alt + start;
-  for (int64_t w = kRun; w < n; w <<= 1) {
+  for (int64_t w = kRunLong; w < n; w <<= 1) {
     for (int64_t a = 0; a < n; a += 2 * w) {
       const int64_t la = min(w, n - a);
       const int64_t lb = min(w, max((int64_t)0, n - a - w));
@@ -694,18 +695,24 @@ __device__ void merge_tile_block(const KWs &ws, int64_t t) {
 }
 
 // Runs of the tiles longer than one wavefront's register sort, listed per
-// sort call (tile, run index) in keys_alt, which the merge passes use only
-// after the runs are sorted; the tiles longer than one run in tile_order
-// (free between the scan and the schedule).  Workgroups take runs, then
-// tiles, from counters, so long tiles spread over the whole chip.
+// sort call in keys_alt (tile ids of the 4096-key runs from word 0, (tile,
+// run index) pairs of the 8192-key runs from word `capacity`), which the
+// merge passes use only after the runs are sorted; the tiles longer than
+// one run in tile_order (free between the scan and the schedule).
+// Workgroups take runs, then tiles, from counters, so long tiles spread over
+// the whole chip.
 __global__ void k_big_reset(KWs ws) {
   ws.hdr->big_count = 0u;
   ws.hdr->big_next = 0u;
   ws.hdr->run_count = 0u;
   ws.hdr->run_next = 0u;
+  ws.hdr->run8_count = 0u;
+  ws.hdr->run8_next = 0u;
 }
 
-__device__ __forceinline__ uint32_t *run_list(const KWs &ws) { return reinterpret_cast<uint32_t *>(ws.keys_alt); }
+__device__ __forceinline__ uint32_t *run_list(const KWs &ws, int run) {
+  return reinterpret_cast<uint32_t *>(ws.keys_alt) + (run == 4096 ? 0 : ws.capacity);
+}
 
 __global__ __launch_bounds__(kBlock) void k_big_collect(KWs ws, int64_t tile_lo, int64_t tile_count) {
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < tile_count;
@@ -713,23 +720,29 @@ __global__ __launch_bounds__(kBlock) void k_big_collect(KWs ws, int64_t tile_lo,
     const int64_t t = tile_lo + b;
     const int64_t n = (int64_t)ws.tile_start[t + 1] - ws.tile_start[t];
     if (n <= kWaveSortMax) continue;
-    const uint32_t runs = (uint32_t)((n + kRun - 1) / kRun);
-    const uint32_t at = atomicAdd(&ws.hdr->run_count, runs);
-    uint32_t *list = run_list(ws);
+    if (n <= 4096) {
+      run_list(ws, 4096)[atomicAdd(&ws.hdr->run_count, 1u)] = (uint32_t)t;
+      continue;
+    }
+    const uint32_t runs = (uint32_t)((n + kRunLong - 1) / kRunLong);
+    const uint32_t at = atomicAdd(&ws.hdr->run8_count, runs);
+    uint32_t *list = run_list(ws, kRunLong);
     for (uint32_t c = 0; c < runs; c++) {
       list[2 * (at + c)] = (uint32_t)t;
       list[2 * (at + c) + 1] = c;
     }
-    if (n > kRun) ws.tile_order[atomicAdd(&ws.hdr->big_count, 1u)] = (uint32_t)t;
+    if (n > kRunLong) ws.tile_order[atomicAdd(&ws.hdr->big_count, 1u)] = (uint32_t)t;
   }
 }
 
-// One level of merges inside a run in LDS: the sorted blocks of w keys are
-// merged in pairs into blocks of 2w.  Each thread produces kRun / kBlock
-// consecutive outputs after one co-rank search (keys are unique), holds them
-// in registers over a barrier and stores them in place.
+// One level of merges inside a run of RUN keys in LDS: the sorted blocks of
+// w keys are merged in pairs into blocks of 2w.  Each of the THREADS threads
+// produces RUN / THREADS consecutive outputs after one co-rank search (keys
+// are unique), holds them in registers over a barrier and stores them in
+// place.
+template <int RUN, int THREADS>
 __device__ __forceinline__ void merge_level_lds(uint64_t *s, int w) {
-  constexpr int kPer = kRun / kBlock;
+  constexpr int kPer = RUN / THREADS;
   const int o0 = (int)threadIdx.x * kPer;
   const int pair = o0 / (2 * w), k0 = o0 - pair * 2 * w;
   const uint64_t *A = s + pair * 2 * w, *B = A + w;
@@ -755,42 +768,45 @@ __device__ __forceinline__ void merge_level_lds(uint64_t *s, int w) {
   __syncthreads();
 }
 
-// Sorts the listed runs: each wavefront sorts its quarter of the run in
-// registers, then two merge levels in LDS give the sorted run.  Missing
-// keys of a short run are padded with distinct values above every key,
-// ascending with the position (depth bits of a finite float stay below
-// 0x7f800000 in the high word), so a quarter of padding only is sorted.
-__global__ __launch_bounds__(kBlock) void k_sort_runs(KWs ws) {
-  constexpr int kQuarter = kRun / 4, R = kQuarter / 64;
-  __shared__ uint64_t s[kRun];
+// Sorts the listed runs of RUN keys: each wavefront sorts its 1024 keys of
+// the run in registers, then merge levels in LDS give the sorted run.
+// Missing keys of a short run are padded with distinct values above every
+// key, ascending with the position (depth bits of a finite float stay below
+// 0x7f800000 in the high word), so a wavefront's share of padding only is
+// sorted.
+template <int RUN>
+__global__ __launch_bounds__(RUN / 16) void k_sort_runs(KWs ws) {
+  constexpr int kWaves = RUN / 1024, kThreads = 64 * kWaves, R = 16;
+  __shared__ uint64_t s[RUN];
   __shared__ uint32_t s_k;
-  const uint32_t count = ws.hdr->run_count;
-  const uint32_t *list = run_list(ws);
+  uint32_t *next = RUN == 4096 ? &ws.hdr->run_next : &ws.hdr->run8_next;
+  const uint32_t count = RUN == 4096 ? ws.hdr->run_count : ws.hdr->run8_count;
+  const uint32_t *list = run_list(ws, RUN);
   const int wave = threadIdx.x >> 6, lane = lane_id();
   for (;;) {
-    if (threadIdx.x == 0) s_k = atomicAdd(&ws.hdr->run_next, 1u);
+    if (threadIdx.x == 0) s_k = atomicAdd(next, 1u);
     __syncthreads();
     const uint32_t k = s_k;
     if (k >= count) break;
-    const int64_t t = list[2 * k];
-    const int64_t c0 = (int64_t)list[2 * k + 1] * kRun;
+    const int64_t t = RUN == 4096 ? list[k] : list[2 * k];
+    const int64_t c0 = RUN == 4096 ? 0 : (int64_t)list[2 * k + 1] * RUN;
     const int64_t start = ws.tile_start[t];
-    const int m = (int)min((int64_t)kRun, (int64_t)ws.tile_start[t + 1] - start - c0);
+    const int m = (int)min((int64_t)RUN, (int64_t)ws.tile_start[t + 1] - start - c0);
     uint64_t *keys = ws.keys + start + c0;
-    const int q0 = wave * kQuarter;
+    const int q0 = wave * 1024;
     uint64_t x[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
       const int e = q0 + lane * R + r;
-      x[r] = e < m ? keys[e] : ~0ull - (uint64_t)(kRun - 1 - e);
+      x[r] = e < m ? keys[e] : ~0ull - (uint64_t)(RUN - 1 - e);
     }
     if (q0 < m) BitonicSort<R, 1, 10>::run(x, lane);  // (uniform per wavefront)
 #pragma unroll
     for (int r = 0; r < R; r++) s[q0 + lane * R + r] = x[r];
     __syncthreads();
-    merge_level_lds(s, kQuarter);
-    merge_level_lds(s, 2 * kQuarter);
-    for (int e = threadIdx.x; e < m; e += kBlock) keys[e] = s[e];
+#pragma unroll
+    for (int w = 1024; w < RUN; w <<= 1) merge_level_lds<RUN, kThreads>(s, w);
+    for (int e = threadIdx.x; e < m; e += kThreads) keys[e] = s[e];
     __syncthreads();
   }
 }
@@ -1168,7 +1184,8 @@ int launch_sort(const KWs &ws, int64_t tile_lo, int64_t tile_count, void *stream
   hipLaunchKernelGGL(k_big_reset, dim3(1), dim3(1), 0, s, ws);
   hipLaunchKernelGGL(k_big_collect, dim3((unsigned)min((tile_count + kBlock - 1) / kBlock, (int64_t)4096)),
                      dim3(kBlock), 0, s, ws, tile_lo, tile_count);
-  hipLaunchKernelGGL(k_sort_runs, dim3(2048), dim3(kBlock), 0, s, ws);
+  hipLaunchKernelGGL(k_sort_runs<4096>, dim3(2048), dim3(256), 0, s, ws);
+  hipLaunchKernelGGL(k_sort_runs<kRunLong>, dim3(1024), dim3(kRunLong / 16), 0, s, ws);
   hipLaunchKernelGGL(k_sort_big, dim3(512), dim3(kSortBigThreads), 0, s, ws);
   return last_err();
 }
