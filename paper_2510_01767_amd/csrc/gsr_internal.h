@@ -28,14 +28,16 @@ struct ViewTable {
 struct WsHeader {
   uint32_t overflow;
   uint32_t nonfinite;
-  uint32_t run_count;     // runs of 4096 keys (tiles of 2049..4096 entries), listed per sort call
   uint32_t union_count;   // Gaussians visible in >= 1 view
   uint32_t isect_total;
-  uint32_t big_count;     // tiles whose lists exceed one wavefront's sort, collected per sort call
-  uint32_t big_next;      // their work counter
-  uint32_t run_next;      // their work counter
-  uint32_t run8_count;    // runs of 8192 keys (the runs of longer tiles)
-  uint32_t run8_next;
+  // the per-tile sort's lists, collected per sort call, and their work
+  // counters: runs of 2048 keys (tiles of 1025..2048 entries), of 4096
+  // (2049..4096), of 8192 (the runs of longer tiles), and the tiles longer
+  // than one run (merged in global memory)
+  uint32_t run2_count, run2_next;
+  uint32_t run_count, run_next;
+  uint32_t run8_count, run8_next;
+  uint32_t big_count, big_next;
   uint32_t isect[GSR_MAX_VIEWS];
   uint32_t visible[GSR_MAX_VIEWS];
   // longest-list-first schedule of the persistent raster: tiles per length

@@ -527,13 +527,13 @@ __global__ __launch_bounds__(kBlock) void k_emit(KWs ws, int64_t n, int n_views,
 // bitonic network: partners closer than R sit in the same lane, the others
 // in lane ^ (j / R), reached by DPP moves for lane distances 1, 2, 4, 8 and
 // by shuffles for 16 and 32.  No LDS traffic besides those shuffles, no
-// barrier.  Longer tiles are sorted as runs: tiles of up to 4096 entries as
-// one run of 4096 keys, longer ones cut into runs of 8192; a workgroup sorts
-// a run with four or eight wavefronts (1024 keys each, in registers as above)
-// and two or three merge levels in LDS.  Tiles longer than one run are then
-// merged run by run in global memory.
+// barrier.  Longer tiles are sorted as runs: tiles of up to 2048 or 4096
+// entries as one run of that many keys, longer ones cut into runs of 8192; a
+// workgroup sorts a run with two, four or eight wavefronts (1024 keys each,
+// in registers as above) and one to three merge levels in LDS.  Tiles
+// longer than one run are then merged run by run in global memory.
 
-constexpr int kWaveSortMax = 2048;  // 64 lanes x 32 keys
+constexpr int kWaveSortMax = 1024;  // 64 lanes x 16 keys
 constexpr int kSortBigThreads = 1024;
 constexpr int kRunLong = 8192;      // the runs of tiles longer than 4096
 
@@ -623,12 +623,10 @@ __device__ __forceinline__ void wave_sort_tile(uint64_t *keys, int n) {
   }
 }
 
-// Four tiles per workgroup, one per wavefront (the whole wavefront stays
-// active through the network); tiles of (n_lo, 64 RMAX] entries.  The
-// largest register count is its own kernel, so that the register budget of
-// the common small tiles stays low.
-template <int RMAX>
-__global__ __launch_bounds__(kBlock) void k_sort_wave(KWs ws, int64_t tile_lo, int64_t tile_count, int n_lo) {
+// Four tiles of at most kWaveSortMax entries per workgroup, one per
+// wavefront (the whole wavefront stays active through the network), the
+// register count sized to the tile.
+__global__ __launch_bounds__(kBlock) void k_sort_wave(KWs ws, int64_t tile_lo, int64_t tile_count) {
   const int64_t groups = (tile_count + 3) / 4;
   const int64_t g = xcd_remap(blockIdx.x, groups);
   if (g >= groups) return;
@@ -637,14 +635,13 @@ __global__ __launch_bounds__(kBlock) void k_sort_wave(KWs ws, int64_t tile_lo, i
   const int64_t t = tile_lo + b;
   const int64_t start = ws.tile_start[t];
   const int n = (int)((int64_t)ws.tile_start[t + 1] - start);
-  if (n <= 1 || n <= n_lo || n > 64 * RMAX) return;
+  if (n <= 1 || n > kWaveSortMax) return;
   uint64_t *keys = ws.keys + start;
-  if (RMAX >= 32) wave_sort_tile<RMAX>(keys, n);  // n > 1024 here
-  else if (n <= 64) wave_sort_tile<1>(keys, n);
+  if (n <= 64) wave_sort_tile<1>(keys, n);
   else if (n <= 128) wave_sort_tile<2>(keys, n);
   else if (n <= 256) wave_sort_tile<4>(keys, n);
   else if (n <= 512) wave_sort_tile<8>(keys, n);
-  else wave_sort_tile<(RMAX >= 16 ? 16 : 8)>(keys, n);
+  else wave_sort_tile<16>(keys, n);
 }
 
 // Merge two sorted runs A[0, la), B[0, lb) into out.  Each thread takes a
@@ -695,9 +692,10 @@ __device__ void merge_tile_block(const KWs &ws, int64_t t) {
 }
 
 // Runs of the tiles longer than one wavefront's register sort, listed per
-// sort call in keys_alt (tile ids of the 4096-key runs from word 0, (tile,
-// run index) pairs of the 8192-key runs from word `capacity`), which the
-// merge passes use only after the runs are sorted; the tiles longer than
+// sort call in keys_alt (tile ids of the 2048-key runs from word 0, of the
+// 4096-key runs from word capacity / 2, (tile, run index) pairs of the
+// 8192-key runs from word `capacity`), which the merge passes use only after
+// the runs are sorted; the tiles longer than
 // one run in tile_order (free between the scan and the schedule).
 // Workgroups take runs, then tiles, from counters, so long tiles spread over
 // the whole chip.
@@ -708,10 +706,12 @@ __global__ void k_big_reset(KWs ws) {
   ws.hdr->run_next = 0u;
   ws.hdr->run8_count = 0u;
   ws.hdr->run8_next = 0u;
+  ws.hdr->run2_count = 0u;
+  ws.hdr->run2_next = 0u;
 }
 
 __device__ __forceinline__ uint32_t *run_list(const KWs &ws, int run) {
-  return reinterpret_cast<uint32_t *>(ws.keys_alt) + (run == 4096 ? 0 : ws.capacity);
+  return reinterpret_cast<uint32_t *>(ws.keys_alt) + (run == 2048 ? 0 : run == 4096 ? ws.capacity / 2 : ws.capacity);
 }
 
 __global__ __launch_bounds__(kBlock) void k_big_collect(KWs ws, int64_t tile_lo, int64_t tile_count) {
@@ -720,6 +720,10 @@ __global__ __launch_bounds__(kBlock) void k_big_collect(KWs ws, int64_t tile_lo,
     const int64_t t = tile_lo + b;
     const int64_t n = (int64_t)ws.tile_start[t + 1] - ws.tile_start[t];
     if (n <= kWaveSortMax) continue;
+    if (n <= 2048) {
+      run_list(ws, 2048)[atomicAdd(&ws.hdr->run2_count, 1u)] = (uint32_t)t;
+      continue;
+    }
     if (n <= 4096) {
       run_list(ws, 4096)[atomicAdd(&ws.hdr->run_count, 1u)] = (uint32_t)t;
       continue;
@@ -779,8 +783,8 @@ __global__ __launch_bounds__(RUN / 16) void k_sort_runs(KWs ws) {
   constexpr int kWaves = RUN / 1024, kThreads = 64 * kWaves, R = 16;
   __shared__ uint64_t s[RUN];
   __shared__ uint32_t s_k;
-  uint32_t *next = RUN == 4096 ? &ws.hdr->run_next : &ws.hdr->run8_next;
-  const uint32_t count = RUN == 4096 ? ws.hdr->run_count : ws.hdr->run8_count;
+  uint32_t *next = RUN == 2048 ? &ws.hdr->run2_next : RUN == 4096 ? &ws.hdr->run_next : &ws.hdr->run8_next;
+  const uint32_t count = RUN == 2048 ? ws.hdr->run2_count : RUN == 4096 ? ws.hdr->run_count : ws.hdr->run8_count;
   const uint32_t *list = run_list(ws, RUN);
   const int wave = threadIdx.x >> 6, lane = lane_id();
   for (;;) {
@@ -788,8 +792,8 @@ __global__ __launch_bounds__(RUN / 16) void k_sort_runs(KWs ws) {
     __syncthreads();
     const uint32_t k = s_k;
     if (k >= count) break;
-    const int64_t t = RUN == 4096 ? list[k] : list[2 * k];
-    const int64_t c0 = RUN == 4096 ? 0 : (int64_t)list[2 * k + 1] * RUN;
+    const int64_t t = RUN <= 4096 ? list[k] : list[2 * k];
+    const int64_t c0 = RUN <= 4096 ? 0 : (int64_t)list[2 * k + 1] * RUN;
     const int64_t start = ws.tile_start[t];
     const int m = (int)min((int64_t)RUN, (int64_t)ws.tile_start[t + 1] - start - c0);
     uint64_t *keys = ws.keys + start + c0;
@@ -1179,11 +1183,11 @@ int launch_sort(const KWs &ws, int64_t tile_lo, int64_t tile_count, void *stream
   if (tile_count <= 0) return 0;
   hipStream_t s = (hipStream_t)stream;
   const dim3 wgrid((unsigned)xcd_grid((tile_count + 3) / 4));
-  hipLaunchKernelGGL(k_sort_wave<16>, wgrid, dim3(kBlock), 0, s, ws, tile_lo, tile_count, 0);
-  hipLaunchKernelGGL(k_sort_wave<32>, wgrid, dim3(kBlock), 0, s, ws, tile_lo, tile_count, 1024);
+  hipLaunchKernelGGL(k_sort_wave, wgrid, dim3(kBlock), 0, s, ws, tile_lo, tile_count);
   hipLaunchKernelGGL(k_big_reset, dim3(1), dim3(1), 0, s, ws);
   hipLaunchKernelGGL(k_big_collect, dim3((unsigned)min((tile_count + kBlock - 1) / kBlock, (int64_t)4096)),
                      dim3(kBlock), 0, s, ws, tile_lo, tile_count);
+  hipLaunchKernelGGL(k_sort_runs<2048>, dim3(4096), dim3(128), 0, s, ws);
   hipLaunchKernelGGL(k_sort_runs<4096>, dim3(2048), dim3(256), 0, s, ws);
   hipLaunchKernelGGL(k_sort_runs<kRunLong>, dim3(1024), dim3(kRunLong / 16), 0, s, ws);
   hipLaunchKernelGGL(k_sort_big, dim3(512), dim3(kSortBigThreads), 0, s, ws);

@@ -5,9 +5,9 @@ of every (view, Gaussian) record, and its visibility bits) are binned and
 ordered by the FP64 oracle's integer binning; the GPU's keys must equal the
 oracle's entry for entry and its tile ranges must be identical.  The scene
 is built so that every length class of the per-tile sort occurs: one
-wavefront in registers up to 1024 and 2048 entries, a workgroup's run sort
-(four or eight wavefronts in registers, then merges in LDS) up to 4096 and
-8192, and runs of 8192 plus merge passes in global memory beyond."""
+wavefront in registers up to 1024 entries, a workgroup's run sort (two,
+four or eight wavefronts in registers, then merges in LDS) up to 2048, 4096
+and 8192, and runs of 8192 plus merge passes in global memory beyond."""
 import numpy as np
 import pytest
 import torch
@@ -21,7 +21,7 @@ from tests import parity
 pytestmark = pytest.mark.gpu
 
 # length classes of the per-tile sort: (lowest, highest, path)
-CLASSES = ((2, 1024, "k_sort_wave<16>"), (1025, 2048, "k_sort_wave<32>"), (2049, 4096, "k_sort_runs<4096>"),
+CLASSES = ((2, 1024, "k_sort_wave"), (1025, 2048, "k_sort_runs<2048>"), (2049, 4096, "k_sort_runs<4096>"),
            (4097, 8192, "k_sort_runs<8192>"), (8193, 1 << 31, "k_sort_runs<8192> + k_sort_big"))
 
 
