@@ -30,13 +30,11 @@ struct WsHeader {
   uint32_t nonfinite;
   uint32_t union_count;   // Gaussians visible in >= 1 view
   uint32_t isect_total;
-  // the per-tile sort's lists, collected per sort call, and their work
-  // counters: runs of 2048 keys (tiles of 1025..2048 entries), of 4096
-  // (2049..4096), of 8192 (the runs of longer tiles), and the tiles longer
-  // than one run (merged in global memory)
-  uint32_t run2_count, run2_next;
-  uint32_t run_count, run_next;
-  uint32_t run8_count, run8_next;
+  // the per-tile sort's lists, collected per sort call: runs of 2048 keys
+  // (tiles of 1025..2048 entries), of 4096 (2049..4096), of 8192 (the runs
+  // of longer tiles), and the tiles longer than one run (merged in global
+  // memory, taken from the work counter big_next)
+  uint32_t run2_count, run_count, run8_count;
   uint32_t big_count, big_next;
   uint32_t isect[GSR_MAX_VIEWS];
   uint32_t visible[GSR_MAX_VIEWS];

@@ -695,47 +695,65 @@ __device__ void merge_tile_block(const KWs &ws, int64_t t) {
 // sort call in keys_alt (tile ids of the 2048-key runs from word 0, of the
 // 4096-key runs from word capacity / 2, (tile, run index) pairs of the
 // 8192-key runs from word `capacity`), which the merge passes use only after
-// the runs are sorted; the tiles longer than
-// one run in tile_order (free between the scan and the schedule).
-// Workgroups take runs, then tiles, from counters, so long tiles spread over
-// the whole chip.
+// the runs are sorted; the tiles longer than one run in tile_order (free
+// between the scan and the schedule).  Workgroups take the runs in a fixed
+// stride (runs of one size cost alike), then the long tiles from a counter,
+// so long tiles spread over the whole chip.
 __global__ void k_big_reset(KWs ws) {
   ws.hdr->big_count = 0u;
   ws.hdr->big_next = 0u;
-  ws.hdr->run_count = 0u;
-  ws.hdr->run_next = 0u;
-  ws.hdr->run8_count = 0u;
-  ws.hdr->run8_next = 0u;
   ws.hdr->run2_count = 0u;
-  ws.hdr->run2_next = 0u;
+  ws.hdr->run_count = 0u;
+  ws.hdr->run8_count = 0u;
 }
 
 __device__ __forceinline__ uint32_t *run_list(const KWs &ws, int run) {
   return reinterpret_cast<uint32_t *>(ws.keys_alt) + (run == 2048 ? 0 : run == 4096 ? ws.capacity / 2 : ws.capacity);
 }
 
+// One atomic per wavefront and list (the lanes' places follow by ballot
+// counts): a single counter hit by every long tile of a 2160p view would
+// serialise on its address.
+__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool take, uint32_t count) {
+  const uint64_t m = __ballot(take);
+  const int lane = lane_id();
+  uint32_t before = 0u, total = 0u;
+  // lanes append `count` entries each; the prefix over lower lanes by shuffles
+  uint32_t c = take ? count : 0u, incl = c;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, (unsigned)off);
+    if (lane >= off) incl += y;
+  }
+  total = __shfl(incl, 63);
+  before = incl - c;
+  uint32_t base = 0u;
+  if (m != 0ull && lane == 0) base = atomicAdd(counter, total);
+  return __shfl(base, 0) + before;
+}
+
 __global__ __launch_bounds__(kBlock) void k_big_collect(KWs ws, int64_t tile_lo, int64_t tile_count) {
-  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < tile_count;
-       b += (int64_t)gridDim.x * blockDim.x) {
+  // (every lane of a wavefront goes through the same iterations: the appends are wavefront-wide)
+  for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < tile_count; b0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = b0 + threadIdx.x;
     const int64_t t = tile_lo + b;
-    const int64_t n = (int64_t)ws.tile_start[t + 1] - ws.tile_start[t];
-    if (n <= kWaveSortMax) continue;
-    if (n <= 2048) {
-      run_list(ws, 2048)[atomicAdd(&ws.hdr->run2_count, 1u)] = (uint32_t)t;
-      continue;
+    const int64_t n = b < tile_count ? (int64_t)ws.tile_start[t + 1] - ws.tile_start[t] : 0;
+    const bool r2 = n > kWaveSortMax && n <= 2048, r4 = n > 2048 && n <= 4096, r8 = n > 4096;
+    const uint32_t runs = r8 ? (uint32_t)((n + kRunLong - 1) / kRunLong) : 0u;
+    const uint32_t a2 = wave_append(&ws.hdr->run2_count, r2, 1u);
+    const uint32_t a4 = wave_append(&ws.hdr->run_count, r4, 1u);
+    const uint32_t a8 = wave_append(&ws.hdr->run8_count, r8, runs);
+    const uint32_t ab = wave_append(&ws.hdr->big_count, n > kRunLong, 1u);
+    if (r2) run_list(ws, 2048)[a2] = (uint32_t)t;
+    if (r4) run_list(ws, 4096)[a4] = (uint32_t)t;
+    if (r8) {
+      uint32_t *list = run_list(ws, kRunLong);
+      for (uint32_t c = 0; c < runs; c++) {
+        list[2 * (a8 + c)] = (uint32_t)t;
+        list[2 * (a8 + c) + 1] = c;
+      }
     }
-    if (n <= 4096) {
-      run_list(ws, 4096)[atomicAdd(&ws.hdr->run_count, 1u)] = (uint32_t)t;
-      continue;
-    }
-    const uint32_t runs = (uint32_t)((n + kRunLong - 1) / kRunLong);
-    const uint32_t at = atomicAdd(&ws.hdr->run8_count, runs);
-    uint32_t *list = run_list(ws, kRunLong);
-    for (uint32_t c = 0; c < runs; c++) {
-      list[2 * (at + c)] = (uint32_t)t;
-      list[2 * (at + c) + 1] = c;
-    }
-    if (n > kRunLong) ws.tile_order[atomicAdd(&ws.hdr->big_count, 1u)] = (uint32_t)t;
+    if (n > kRunLong) ws.tile_order[ab] = (uint32_t)t;
   }
 }
 
@@ -782,16 +800,11 @@ template <int RUN>
 __global__ __launch_bounds__(RUN / 16) void k_sort_runs(KWs ws) {
   constexpr int kWaves = RUN / 1024, kThreads = 64 * kWaves, R = 16;
   __shared__ uint64_t s[RUN];
-  __shared__ uint32_t s_k;
-  uint32_t *next = RUN == 2048 ? &ws.hdr->run2_next : RUN == 4096 ? &ws.hdr->run_next : &ws.hdr->run8_next;
   const uint32_t count = RUN == 2048 ? ws.hdr->run2_count : RUN == 4096 ? ws.hdr->run_count : ws.hdr->run8_count;
   const uint32_t *list = run_list(ws, RUN);
   const int wave = threadIdx.x >> 6, lane = lane_id();
-  for (;;) {
-    if (threadIdx.x == 0) s_k = atomicAdd(next, 1u);
-    __syncthreads();
-    const uint32_t k = s_k;
-    if (k >= count) break;
+  // runs of one size cost alike: workgroups take them in a fixed stride
+  for (uint32_t k = blockIdx.x; k < count; k += gridDim.x) {
     const int64_t t = RUN <= 4096 ? list[k] : list[2 * k];
     const int64_t c0 = RUN <= 4096 ? 0 : (int64_t)list[2 * k + 1] * RUN;
     const int64_t start = ws.tile_start[t];

@@ -607,11 +607,28 @@ __global__ __launch_bounds__(kOrderBins) void k_order_scan(KWs ws) {
   ws.hdr->order_cursor[k] = s[k] - x;
 }
 
+// Each workgroup places its tiles with one device atomic per bin it holds
+// (the ranks inside the workgroup from LDS atomics): the bins of the many
+// short or empty tiles would otherwise take one atomic per tile on a single
+// address.
 __global__ __launch_bounds__(kBlock) void k_order_scatter(KWs ws) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ws.tiles_total;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t pos = atomicAdd(&ws.hdr->order_cursor[order_bin(ws, t)], 1u);
-    ws.tile_order[pos] = (uint32_t)t;
+  __shared__ uint32_t s_cnt[kOrderBins], s_base[kOrderBins];
+  for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < ws.tiles_total; t0 += (int64_t)gridDim.x * blockDim.x) {
+    for (int k = threadIdx.x; k < kOrderBins; k += blockDim.x) s_cnt[k] = 0u;
+    __syncthreads();
+    const int64_t t = t0 + threadIdx.x;
+    int bin = -1;
+    uint32_t off = 0u;
+    if (t < ws.tiles_total) {
+      bin = order_bin(ws, t);
+      off = atomicAdd(&s_cnt[bin], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kOrderBins; k += blockDim.x)
+      if (s_cnt[k]) s_base[k] = atomicAdd(&ws.hdr->order_cursor[k], s_cnt[k]);
+    __syncthreads();
+    if (bin >= 0) ws.tile_order[s_base[bin] + off] = (uint32_t)t;
+    __syncthreads();
   }
 }
 

@@ -12,6 +12,11 @@ from tests import parity
 
 pytestmark = pytest.mark.gpu
 
+# Two GPU runs of the same arithmetic whose float32 atomic sums (the 2D
+# gradients, up to a few hundred terms per entry) add up in different orders
+# differ by ~1e-6 relative L2 on the small, cancelling quaternion gradient.
+ATOMIC_ORDER_RTOL = 1e-5
+
 
 def announce(*a):
     print("[gpu-case]", *a, flush=True)
@@ -181,9 +186,11 @@ def test_batched_equals_plain_and_is_deterministic(ragged):
     rb, params, cams, targets, _ = run_step(ragged, mode="batched")
     ip, ib = rp.images.cpu().numpy(), rb.images.cpu().numpy()
     assert np.array_equal(ip, ib)
+    # the same arithmetic; the tiles run in another order, so the float32
+    # atomic sums of the 2D gradients add up in another order
     for k in rp.grads:
         a, b = rp.grads[k].cpu().numpy(), rb.grads[k].cpu().numpy()
-        assert np.linalg.norm(a - b) <= 1e-6 * max(np.linalg.norm(b), 1e-30), k
+        assert np.linalg.norm(a - b) <= ATOMIC_ORDER_RTOL * max(np.linalg.norm(b), 1e-30), k
     rb.step_l1(params, cams, targets, stats=False)
     torch.cuda.synchronize()
     assert np.array_equal(rb.images.cpu().numpy(), ib)
@@ -204,7 +211,7 @@ def test_storage_order_does_not_change_results(ragged, mode):
     for k in rr.grads:
         a = rm.grads[k].cpu().numpy()
         b = rr.grads[k].cpu().numpy()[..., perm]
-        assert np.linalg.norm(a - b) <= 1e-6 * max(np.linalg.norm(b), 1e-30), k
+        assert np.linalg.norm(a - b) <= ATOMIC_ORDER_RTOL * max(np.linalg.norm(b), 1e-30), k
     assert np.array_equal(rm.count.cpu().numpy(), rr.count.cpu().numpy()[perm])
     ora = ora_step(sm)
     ex = parity.excluded_gaussians(ora, sm.n, parity.opts_for((16, 16)), sm.targets)
@@ -243,10 +250,9 @@ def test_forward_backward_split_equals_fused_l1(ragged):
     r2.backward(params, cams, d.contiguous())
     torch.cuda.synchronize()
     # the same arithmetic; only the order of the float32 atomic sums differs
-    # (as between the stored and recomputed reverse passes)
     for k in rf.grads:
         a, b = r2.grads[k].cpu().numpy(), rf.grads[k].cpu().numpy()
-        assert np.linalg.norm(a - b) <= 1e-5 * max(np.linalg.norm(b), 1e-30), k
+        assert np.linalg.norm(a - b) <= ATOMIC_ORDER_RTOL * max(np.linalg.norm(b), 1e-30), k
 
 
 def test_visibility_mask_matches_oracle(ragged):
@@ -290,7 +296,7 @@ def test_graph_capture_replays_match_eager(ragged):
         assert abs(float(r.loss.item()) - loss0) <= 1e-7 * abs(loss0)
         for k in g0:
             a = r.grads[k].cpu().numpy()
-            assert np.linalg.norm(a - g0[k]) <= 1e-6 * max(np.linalg.norm(g0[k]), 1e-30), (rep, k)
+            assert np.linalg.norm(a - g0[k]) <= ATOMIC_ORDER_RTOL * max(np.linalg.norm(g0[k]), 1e-30), (rep, k)
         # eager work between replays
         r.forward(params, cams)
         torch.cuda.synchronize()
@@ -358,7 +364,7 @@ def test_autograd_function_returns_library_gradients(ragged):
     for k in leaves:
         a = leaves[k].grad.cpu().numpy()
         b = 2.0 * r2.grads[k].cpu().numpy()
-        assert np.linalg.norm(a - b) <= 1e-6 * max(np.linalg.norm(b), 1e-30), k
+        assert np.linalg.norm(a - b) <= ATOMIC_ORDER_RTOL * max(np.linalg.norm(b), 1e-30), k
 
 
 def test_render_backward_after_a_second_render_raises_or_matches_oracle(ragged):

@@ -68,10 +68,13 @@ def check_same(a, b):
     assert np.array_equal(a["images"], b["images"])
     assert a["loss"] == b["loss"]
     assert np.array_equal(a["count"], b["count"])
+    # the same kernels; the float32 atomic sums of the 2D gradients (and the
+    # statistics built on them) may add up in another order between two runs,
+    # ~1e-6 relative L2 on the small, cancelling quaternion gradient
     rel = lambda x, y: np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-30)
-    assert rel(a["S"], b["S"]) <= 1e-6
+    assert rel(a["S"], b["S"]) <= 1e-5
     for k in a["grads"]:
-        assert rel(a["grads"][k], b["grads"][k]) <= 1e-6, k
+        assert rel(a["grads"][k], b["grads"][k]) <= 1e-5, k
 
 
 @pytest.mark.parametrize("mode", ["batched", "plain"])
