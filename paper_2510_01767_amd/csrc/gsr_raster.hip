@@ -520,8 +520,11 @@ __global__ __launch_bounds__(kBlock) void k_raster_bwd(KWs ws, KOpts o, int64_t 
 // consecutive workgroups to the 8 XCDs in turn, so each counter is shared by
 // one XCD's workgroups instead of one counter by the whole chip.  The grid
 // is a multiple of 8, so every class has workgroups and every tile is taken.
+// The reduce-scatter form (RED 0) is held to 64 VGPRs, eight wavefronts per
+// SIMD, which its LDS also allows (a few registers spill); the LDS
+// accumulator forms are limited by their LDS anyway.
 template <int TW, int TH, int B, int RED, bool HIST>
-__global__ __launch_bounds__(kBlock) void k_fused(KWs ws, KOpts o, const float *targets, float *images,
+__global__ __launch_bounds__(kBlock, RED == 0 && !HIST ? 8 : 1) void k_fused(KWs ws, KOpts o, const float *targets, float *images,
                                                   int n_views, const uint32_t *order) {
   __shared__ LdsBatch<B> s_rec;
   __shared__ uint32_t s_idx[B];
