@@ -45,6 +45,8 @@ struct WsHeader {
   // persistent raster work counters, one per workgroup class (blockIdx mod
   // 8), each in a 128-byte line of its own
   uint32_t queue[8][32];
+  // per-view loss sums (scaled), added up in view order for the loss
+  double view_loss[GSR_MAX_VIEWS];
 };
 constexpr int kOrderBins = 1024;
 

@@ -843,27 +843,35 @@ __global__ __launch_bounds__(kSortBigThreads) void k_sort_big(KWs ws) {
 
 // --------------------------------------------------------------- loss total
 
-// Deterministic: fixed thread mapping and reduction tree, double accumulation.
-__global__ __launch_bounds__(kScanThreads) void k_loss(KWs ws, int n_views, float *loss) {
+// Deterministic: fixed thread mapping and reduction tree, double
+// accumulation.  One workgroup per view sums its tiles' losses; one thread
+// then adds the views in order.
+__global__ __launch_bounds__(kScanThreads) void k_loss_views(KWs ws) {
   constexpr int kWaves = kScanThreads / 64;
   __shared__ double s_w[kWaves];
-  double total = 0.0;
-  for (int v = 0; v < n_views; v++) {
-    const ViewInfo vi = ws.views[v];
-    const int64_t nt = (int64_t)vi.tiles_x * vi.tiles_y;
-    double a = 0.0;
-    for (int64_t k = threadIdx.x; k < nt; k += kScanThreads) a += (double)ws.tile_loss[vi.tile_base + k];
+  const int v = blockIdx.x;
+  const ViewInfo vi = ws.views[v];
+  const int64_t nt = (int64_t)vi.tiles_x * vi.tiles_y;
+  double a = 0.0;
+  for (int64_t k = threadIdx.x; k < nt; k += kScanThreads) a += (double)ws.tile_loss[vi.tile_base + k];
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1) a += __shfl_xor(a, m);
-    __syncthreads();
-    if (lane_id() == 0) s_w[threadIdx.x >> 6] = a;
-    __syncthreads();
+  for (int m = 1; m < 64; m <<= 1) a += __shfl_xor(a, m);
+  if (lane_id() == 0) s_w[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < kWaves; w++) t += s_w[w];
-    total += t * (double)vi.loss_scale;
+    ws.hdr->view_loss[v] = t * (double)vi.loss_scale;
   }
-  if (threadIdx.x == 0) *loss = (float)total;
+}
+
+__global__ void k_loss_total(KWs ws, int n_views, float *loss) {
+  if (threadIdx.x == 0) {
+    double total = 0.0;
+    for (int v = 0; v < n_views; v++) total += ws.hdr->view_loss[v];
+    *loss = (float)total;
+  }
 }
 
 // -------------------------------------------------------------- project_bwd
@@ -1221,7 +1229,8 @@ int launch_project_bwd(const KParams &p, const gsr_camera *cams, const KOpts &o,
 }
 
 int launch_loss(const KWs &ws, int n_views, float *loss, void *stream) {
-  hipLaunchKernelGGL(k_loss, dim3(1), dim3(kScanThreads), 0, (hipStream_t)stream, ws, n_views, loss);
+  hipLaunchKernelGGL(k_loss_views, dim3((unsigned)n_views), dim3(kScanThreads), 0, (hipStream_t)stream, ws);
+  hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, (hipStream_t)stream, ws, n_views, loss);
   return last_err();
 }
 
