@@ -711,11 +711,10 @@ __device__ __forceinline__ uint32_t *run_list(const KWs &ws, int run) {
   return reinterpret_cast<uint32_t *>(ws.keys_alt) + (run == 2048 ? 0 : run == 4096 ? ws.capacity / 2 : ws.capacity);
 }
 
-// One atomic per wavefront and list (the lanes' places follow by ballot
-// counts): a single counter hit by every long tile of a 2160p view would
-// serialise on its address.
+// One atomic per wavefront and list, the lanes' places following from a
+// prefix sum over the wavefront: a single counter hit by every long tile of
+// a 2160p view would serialise on its address.
 __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool take, uint32_t count) {
-  const uint64_t m = __ballot(take);
   const int lane = lane_id();
   uint32_t before = 0u, total = 0u;
   // lanes append `count` entries each; the prefix over lower lanes by shuffles
@@ -728,7 +727,7 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool take, ui
   total = __shfl(incl, 63);
   before = incl - c;
   uint32_t base = 0u;
-  if (m != 0ull && lane == 0) base = atomicAdd(counter, total);
+  if (total != 0u && lane == 0) base = atomicAdd(counter, total);
   return __shfl(base, 0) + before;
 }
 
