@@ -101,6 +101,19 @@ def b_alg_fused(vis, isect, pixels):
     return 80 * isect + 52 * pixels + 36 * vis
 
 
+def slot_grad2d(slots, conic):
+    """2D gradient (dmean 2, dconic 3, dopacity, dcolour 3) from GPU record
+    slots, whose words 0..4 hold the moments of dL/dp over the pixel offsets
+    d (gp dx, gp dy, gp dx^2, gp dx dy, gp dy^2; p = -d^T Q d / 2): with the
+    conic Q = (A, B, C), dL/dmean2d = Q (m0, m1) and dL/dQ = -(m2/2, m3, m4/2)."""
+    m = np.asarray(slots, np.float64)[:, :9]
+    A, B, C = (np.asarray(conic, np.float64)[j] for j in range(3))
+    out = m.copy()
+    out[:, 0], out[:, 1] = A * m[:, 0] + B * m[:, 1], B * m[:, 0] + C * m[:, 1]
+    out[:, 2], out[:, 3], out[:, 4] = -0.5 * m[:, 2], -m[:, 3], -0.5 * m[:, 4]
+    return out
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -526,7 +539,7 @@ def main():
                 visv = fo["records"][0]["visible"].astype(bool)
                 ex = oracle.touching(fo, [amb | kink], o)[:n] | (fo["records"][0]["margin"] < oracle.DELTA_GAUSS)
                 sel = visv & ~ex
-                g2d = g2d_all[v * n:(v + 1) * n][sel].astype(np.float64)
+                g2d = slot_grad2d(g2d_all[v * n:(v + 1) * n][sel], fo["records"][0]["conic"][:, sel])
                 go = bo["g2d"].T[sel]
                 g_rel = float(np.linalg.norm(g2d - go) / np.linalg.norm(go))
                 rms = np.sqrt(np.mean(go * go, axis=0))

@@ -160,9 +160,13 @@ typedef struct gsr_counts {
 } gsr_counts;
 
 /* Internal byte offsets of the workspace (for tests and profiling).  grad2d
- * holds one slot of GSR_SLOT_FLOATS 32-bit words per record: the record's 2D
- * gradient (dmean 2, dconic 3, dopacity, dcolour 3) in words 0..8, then its
- * in-tile ranks (4 x u32), tile rectangle (2 x u32) and depth bits. */
+ * holds one slot of GSR_SLOT_FLOATS 32-bit words per record: in words 0..8
+ * what the reverse raster pass sums for the record, the moments of dL/dp over
+ * the pixel offsets d = pixel - mean2d (gp dx, gp dy, gp dx^2, gp dx dy,
+ * gp dy^2, with p = -d^T Q d / 2 the exponent of the Gaussian's alpha), then
+ * dL/dopacity and dL/dcolour (3); its 2D gradient is dL/dmean2d = Q (m0, m1),
+ * dL/d(A, B, C) = -(m2 / 2, m3, m4 / 2).  Then its in-tile ranks (4 x u32),
+ * tile rectangle (2 x u32) and depth bits. */
 #define GSR_SLOT_FLOATS 16
 typedef struct gsr_layout {
   size_t header, view_table, view_bits, records, grad2d, tile_count, tile_start, tile_fill,

@@ -311,7 +311,7 @@ __device__ __forceinline__ void sh_grad(T x, T y, T z, const T *w, T g[3]) {
 // identical float32 expression and replay the same skip / stop decisions.
 struct PairAlpha {
   float dx, dy, G, raw, alpha;
-  float t, cdy;  // a dx + b dy and c dy, reused by the reverse partials
+  float t, cdy;  // a dx + b dy and c dy (parts of the exponent)
 };
 
 // The record holds the exponent's coefficients in base 2, so the exponent
@@ -332,9 +332,12 @@ __device__ __forceinline__ PairAlpha pair_alpha(float pxc, float pyc, const floa
   const float e = __builtin_amdgcn_exp2f(p2);
   a.G = (p2 > 0.0f || p2 < pmin2) ? -1.0f : e;  // G < 0 marks a skipped pair
   a.raw = r1.w * a.G;
-  // min(raw, alpha_max) as one v_med3_f32: the median of raw, alpha_max and
-  // -inf, without the quieting a minnum of a non-canonical operand takes
-  a.alpha = __builtin_amdgcn_fmed3f(a.raw, alpha_max, -__builtin_huge_valf());
+  // min(raw, alpha_max) as a signed integer minimum of the bit patterns:
+  // alpha_max > 0, and raw is either >= 0 (where integer and float order
+  // agree) or negative (sign bit set, so the integer minimum picks it, as the
+  // float one does).  One operation, with no canonicalisation of alpha_max
+  // inside the loop (a float minimum in IEEE mode re-quiets its operand).
+  a.alpha = __int_as_float(min(__float_as_int(a.raw), __float_as_int(alpha_max)));
   return a;
 }
 

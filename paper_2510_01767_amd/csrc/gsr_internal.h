@@ -83,8 +83,10 @@ struct KGrads {
 //        reach of the alpha >= alpha_min ellipse in pixels (float bits)
 constexpr int kRecordFloat4 = 4;
 // Slot of one record, 64 bytes (16 x 32 bit, one memory segment):
-//   [0, 9)   2D gradient: dmean (2), dconic (3), dopacity, dcolour (3), summed
-//            by the reverse raster pass (cleared by the projection)
+//   [0, 9)   summed by the reverse raster pass (cleared by the projection):
+//            moments of dL/dp over the pixel offsets d (gp dx, gp dy,
+//            gp dx^2, gp dx dy, gp dy^2), dopacity, dcolour (3); the reverse
+//            projection turns the moments into dmean and dconic
 //   [9, 13)  in-tile ranks of the record's first four tiles (u32)
 //   [13, 15) tile rectangle (x0 | y0 << 16, x1 | y1 << 16)
 //   [15]     depth (camera z, float bits: the sort key's high word)

@@ -914,12 +914,17 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(KParams p, const gsr_cam
     project_view<false>(gf, cam, o, P);  // visible by construction of view_bits
     const float4 *g2 = reinterpret_cast<const float4 *>(ws.grad2d + ((int64_t)v * n + i) * kGrad2dStride);
     const float4 q0 = g2[0], q1 = g2[1];
-    const double gmx = q0.x, gmy = q0.y, gA = q0.z, gB = q0.w, gC = q1.x, go = q1.y;
+    // the reverse raster's moments of dL/dp over the pixel offsets d (sums of
+    // gp dx, gp dy, gp dx^2, gp dx dy, gp dy^2; p = -d^T Q d / 2) give the 2D
+    // gradient: dL/dmean = Q (m0, m1), dL/d(A, B, C) = -(m2 / 2, m3, m4 / 2)
+    const double QA = P.A, QB = P.B, QC = P.C;
+    const double m0 = q0.x, m1 = q0.y;
+    const double gmx = QA * m0 + QB * m1, gmy = QB * m0 + QC * m1;
+    const double gA = -0.5 * (double)q0.z, gB = -(double)q0.w, gC = -0.5 * (double)q1.x, go = q1.y;
     Sacc += (float)(stat_scale * sqrt(gmx * gmx + gmy * gmy));
     cnt += 1;
     gopac += go;
     // conic -> 2D covariance:  dL/dS = -Q G_Q Q with G_Q = [[gA, gB/2], [gB/2, gC]]
-    const double QA = P.A, QB = P.B, QC = P.C;
     const double h = 0.5 * gB;
     const double m00 = gA * QA + h * QB, m01 = gA * QB + h * QC;  // G_Q Q
     const double m10 = h * QA + gC * QB, m11 = h * QB + gC * QC;

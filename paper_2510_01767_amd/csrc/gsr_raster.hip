@@ -15,7 +15,9 @@
 // scenes most entries of a tile list miss most sub-blocks, which is where
 // the time would otherwise go.
 //
-// Reverse pass.  Each row reduces the nine 2D partials of its entry by a
+// Reverse pass.  Each row reduces the nine per-pixel terms of its entry
+// (the moments of dL/dp over the pixel offset, which the reverse projection
+// maps through the record's conic, then dL/dopacity and dL/dcolour) by a
 // reduce-scatter over its 16 lanes; lanes 0..8 then either add the sums to
 // the record's gradient slot with device atomics, or (the other variants the
 // autotuner weighs) into a per-batch LDS accumulator flushed with one device
@@ -164,7 +166,7 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
                                              uint32_t *n_blend = nullptr) {
   const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
   // canonical once, so the per-pair min needs no quieting of it
-  const float amax = __builtin_canonicalizef(o.alpha_max);
+  const float amax = o.alpha_max;
   const int wave = threadIdx.x >> 6, row = ((int)threadIdx.x & 63) >> 4;
   T = 1.0f;
   C[0] = C[1] = C[2] = 0.0f;
@@ -218,7 +220,7 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
   if (!stopped) last = c.inside ? (int)(c.end - c.start) : 0;
 }
 
-// Reduce-scatter of the nine partials over each 16-lane row: four butterfly
+// Reduce-scatter of the nine terms over each 16-lane row: four butterfly
 // steps between lanes i and i ^ 7, i ^ 1, i ^ 2, i ^ 8 (row_half_mirror, two
 // quad permutations, row_ror:8), each step leaving a lane half of the
 // components it carried, summed with its partner's.  Lanes 0..8 of a row end
@@ -253,10 +255,12 @@ __device__ __forceinline__ float row_reduce_scatter(const float v[9], bool lb0, 
 
 // Back-to-front reverse pass of one tile.  g = dL/dC_out of this lane's
 // pixel, T its final transmittance (recovered entry by entry unless the
-// forward stored it).
-//   RED = 0: per row entry, the reduce-scatter of the nine partials over the
+// forward stored it).  Each contributing pair gives nine terms, summed per
+// entry into its slot: the five moments of dL/dp over the pixel offset, then
+// dL/dopacity and dL/dcolour.
+//   RED = 0: per row entry, the reduce-scatter of the nine terms over the
 //            row and one device atomic per component from lanes 0..8.
-//   RED = 1: contributing lanes add their partials into an LDS accumulator
+//   RED = 1: contributing lanes add their terms into an LDS accumulator
 //            of the batch (ds_add_f32, combining the four wavefronts); one
 //            device atomic per non-zero (entry, component) after the batch.
 //   RED = 2, 3, 4: as 1 after DPP sums over lane quads (2), over 16-lane
@@ -270,7 +274,7 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
                                               int *s_max, float T, int last, const float g[3],
                                               const float *hist, Resident res) {
   const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
-  const float amax = __builtin_canonicalizef(o.alpha_max);  // as in the forward pass
+  const float amax = o.alpha_max;  // as in the forward pass
   const int wave = threadIdx.x >> 6, lane = lane_id();
   // the reduce-scatter's lane roles (RED = 4): which component lane q of a
   // 16-lane row ends with, -1 for none
@@ -323,7 +327,7 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
       const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, amax);
       const bool contrib = valid && jj < jj_last && a.alpha >= o.alpha_min;
       if (__ballot(contrib) == 0ull) continue;
-      // Every lane evaluates the partials (all finite: alpha <= 0.99).  The
+      // Every lane evaluates the terms (all finite: alpha <= 0.99).  The
       // non-contributing lanes take alpha = 0 here: 1 / (1 - 0) is exactly 1,
       // so their T and suffix stay as they are and they add exact zeros.
       // 1 / (1 - alpha) by the hardware reciprocal (1 ulp): T and the
@@ -339,17 +343,22 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
       gS = __fmaf_rn(wgt, gc, gS);
 #pragma unroll
       for (int ch = 0; ch < 3; ch++) v[6 + ch] = g[ch] * wgt;
-      // the geometric partials vanish where alpha is clamped at alpha_max
+      // the geometric terms vanish where alpha is clamped at alpha_max
       const float dLdam = (contrib && a.raw < o.alpha_max) ? dLda : 0.0f;
       const float gp = dLdam * a.alpha;  // dL/dp
       v[5] = dLdam * a.G;
-      // dp/dmean = (A dx + B dy, B dx + C dy) = -(2 a dx + b dy, b dx + 2 c dy) ln 2
-      const float gq = gp * -0.693147180559945309f;
-      v[0] = gq * __fmaf_rn(R.r1.x, a.dx, a.t);
-      v[1] = gq * __fmaf_rn(R.r1.y, a.dx, a.cdy + a.cdy);
-      v[2] = -0.5f * gp * a.dx * a.dx;
-      v[3] = -gp * a.dx * a.dy;
-      v[4] = -0.5f * gp * a.dy * a.dy;
+      // the moments of dL/dp over the pixel offsets d = pixel - mean:
+      // sum gp dx, gp dy, gp dx^2, gp dx dy, gp dy^2.  The geometric 2D
+      // gradient is linear in them with the record's conic Q as coefficients
+      // (dL/dmean = Q (m0, m1), dL/dQ = -(m2 / 2, m3, m4 / 2)), so the
+      // reverse projection applies Q once per record instead of every pixel
+      // applying it here.
+      const float gpx = gp * a.dx, gpy = gp * a.dy;
+      v[0] = gpx;
+      v[1] = gpy;
+      v[2] = gpx * a.dx;
+      v[3] = gpx * a.dy;
+      v[4] = gpy * a.dy;
       T = Ti;
       if (RED == 0) {
         // the row's reduce-scatter, then one device atomic per component from

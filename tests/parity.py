@@ -40,6 +40,28 @@ def ora_grad_groups(grads: np.ndarray) -> dict:
                 sh_dc=grads[11:14], sh_rest=grads[14:])
 
 
+def slot_grad2d(slots, conic):
+    """The 2D gradient (dmean 2, dconic 3, dopacity, dcolour 3) of GPU record slots.
+
+    Words 0..4 of a slot hold what the reverse raster pass sums per record:
+    the moments of dL/dp over the pixel offsets d = pixel - mean2d (gp dx,
+    gp dy, gp dx^2, gp dx dy, gp dy^2 with gp = dL/dp), where the exponent is
+    p = -(A dx^2 + 2 B dx dy + C dy^2) / 2 (Sec. 3.2, the Gaussian's alpha).
+    So dL/dmean2d = -dp/dd summed = (A m0 + B m1, B m0 + C m1) and
+    dL/d(A, B, C) = -(m2 / 2, m3, m4 / 2); words 5..8 are dL/dopacity and
+    dL/dcolour as they are.  slots: [k, >= 9]; conic: [3, k] (A, B, C), the
+    oracle's conic of the same records."""
+    m = np.asarray(slots, np.float64)[:, :9]
+    A, B, C = (np.asarray(conic, np.float64)[j] for j in range(3))
+    out = m.copy()
+    out[:, 0] = A * m[:, 0] + B * m[:, 1]
+    out[:, 1] = B * m[:, 0] + C * m[:, 1]
+    out[:, 2] = -0.5 * m[:, 2]
+    out[:, 3] = -m[:, 3]
+    out[:, 4] = -0.5 * m[:, 4]
+    return out
+
+
 def compare_images(gpu_images, ora, report=None):
     """gpu_images: list of [3, H, W] arrays; ora: oracle.forward/step_l1 output."""
     n_amb = 0

@@ -110,7 +110,7 @@ def check_sampled_views(s, r, views):
         ex = parity.excluded_gaussians(fo, n, opts, [s.targets[v]])
         parity.assert_excluded_fraction(ex, vis, rep)
         sel = vis & ~ex
-        gg = g2d_all[v * n:(v + 1) * n, :9].cpu().numpy().astype(np.float64)[sel]
+        gg = parity.slot_grad2d(g2d_all[v * n:(v + 1) * n, :9].cpu().numpy()[sel], fo["records"][0]["conic"][:, sel])
         go = bo["g2d"].T[sel]
         for k in range(9):
             a_, b_ = gg[:, k], go[:, k]
@@ -246,7 +246,7 @@ def test_config4_window_matches_oracle():
     sel = np.nonzero(inner & ~ex)[0]
     L = r.layout
     g2d = r.ws_tensor("grad2d", torch.float32, C.GSR_SLOT_FLOATS * L.vn).view(-1, C.GSR_SLOT_FLOATS)
-    gg = g2d[v * n + torch.from_numpy(sel).cuda(), :9].cpu().numpy().astype(np.float64)
+    gg = parity.slot_grad2d(g2d[v * n + torch.from_numpy(sel).cuda(), :9].cpu().numpy(), rec["conic"][:, sel])
     go = bo["g2d"].T[sel]
     assert sel.size > 1000, sel.size
     for k in range(9):
