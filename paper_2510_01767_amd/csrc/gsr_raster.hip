@@ -165,7 +165,6 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
                                              float *D = nullptr, uint32_t *n_eval = nullptr,
                                              uint32_t *n_blend = nullptr) {
   const float pxc = (float)c.px + 0.5f, pyc = (float)c.py + 0.5f;
-  // canonical once, so the per-pair min needs no quieting of it
   const float amax = o.alpha_max;
   const int wave = threadIdx.x >> 6, row = ((int)threadIdx.x & 63) >> 4;
   T = 1.0f;
