@@ -63,6 +63,9 @@ typedef int32_t gsr_status;
 #define GSR_ERR_STATE 6 /* call order: backward before forward, launch before capture */
 
 #define GSR_MAX_VIEWS 32
+/* Largest Gaussian count a plan accepts: the per-Gaussian kernels run one
+ * thread per Gaussian on grids of at most 2^20 workgroups of 256 threads. */
+#define GSR_MAX_GAUSSIANS ((int64_t)1 << 28)
 #define GSR_MAX_IMAGE_SIDE 16384
 
 /* Execution form. */
@@ -120,7 +123,7 @@ typedef struct gsr_options {
 
 /* Static shape of a problem; widths/heights are host arrays [n_views]. */
 typedef struct gsr_problem {
-  int64_t n;
+  int64_t n;         /* 1..GSR_MAX_GAUSSIANS, and n * n_views < 2^32 */
   int32_t sh_degree; /* 0..3; K = (sh_degree + 1)^2 coefficients per channel */
   int32_t n_views;   /* 1..GSR_MAX_VIEWS */
   const int32_t *widths;

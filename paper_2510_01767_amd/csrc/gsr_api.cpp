@@ -129,7 +129,7 @@ gsr_status validate_options(const gsr_options &o) {
 
 gsr_status validate_problem(const gsr_problem *pr) {
   if (!pr || !pr->widths || !pr->heights) return GSR_ERR_INVALID_ARG;
-  if (pr->n <= 0 || pr->sh_degree < 0 || pr->sh_degree > 3) return GSR_ERR_INVALID_ARG;
+  if (pr->n <= 0 || pr->n > GSR_MAX_GAUSSIANS || pr->sh_degree < 0 || pr->sh_degree > 3) return GSR_ERR_INVALID_ARG;
   if (pr->n_views < 1 || pr->n_views > GSR_MAX_VIEWS) return GSR_ERR_INVALID_ARG;
   if (pr->n * (int64_t)pr->n_views >= ((int64_t)1 << 32)) return GSR_ERR_INVALID_ARG;
   for (int v = 0; v < pr->n_views; v++)

@@ -63,6 +63,7 @@ def test_defaults():
     lambda p, o: setattr(p, "n_views", 0),
     lambda p, o: setattr(p, "n_views", 33),
     lambda p, o: setattr(p, "n", 1 << 31),  # n * n_views >= 2^32
+    lambda p, o: setattr(p, "n", (1 << 28) + 1),  # above GSR_MAX_GAUSSIANS (per-Gaussian grids)
     lambda p, o: p.widths.__setitem__(0, 0),
     lambda p, o: p.heights.__setitem__(1, 16385),
     lambda p, o: setattr(o, "tile_h", 8),
@@ -82,6 +83,14 @@ def test_invalid_arguments_are_rejected(mutate):
     mutate(p, o)
     s, plan = create(p, o)
     assert s == C.GSR_ERR_INVALID_ARG and not plan.value
+
+
+def test_largest_gaussian_count_is_accepted():
+    p = problem()
+    p.n = 1 << 28
+    s, plan = create(p, C.gsr_default_options())
+    assert s == C.GSR_OK and plan.value
+    C.load().gsr_plan_destroy(plan)
 
 
 def test_null_problem():
