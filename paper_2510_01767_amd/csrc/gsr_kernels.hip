@@ -908,6 +908,10 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(KParams p, const gsr_cam
   uint32_t cnt = 0;
   const double stat_scale = o.stat_scale;
   for (uint32_t b = bits; b; b &= b - 1) {
+    // the chain rule below only feeds gradients: multiply-adds may fuse (the
+    // projection it starts from, and the colour replay after the loop, whose
+    // clamp must take the forward's decision, are not fused)
+#pragma clang fp contract(fast)
     const int v = __ffs(b) - 1;
     const Cam64 &cam = s_cam[v];
     Proj P;
@@ -1035,6 +1039,8 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(KParams p, const gsr_cam
       gmu[2] += (double)(gd[2] - dot * z) * idn;
     }
   }
+  {
+#pragma clang fp contract(fast)
   Geo g;
   load_geo(p, i, g);
   // Sigma = Rq diag(s^2) Rq^T  (gSig holds dL/dSigma_ij for i <= j, off-diagonals doubled)
@@ -1103,6 +1109,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(KParams p, const gsr_cam
   }
   if (stat_S) stat_S[i] += Sacc;
   if (stat_n) stat_n[i] += cnt;
+  }
 }
 
 // -------------------------------------------------------------- visibility
