@@ -312,25 +312,31 @@ __device__ __forceinline__ void sh_grad(T x, T y, T z, const T *w, T g[3]) {
 struct PairAlpha {
   float dx, dy, G, raw, alpha;
   float t, cdy;  // a dx + b dy and c dy (parts of the exponent)
+  bool in;       // p <= 0: a pair with a positive exponent (rounding) is skipped
 };
 
 // The record holds the exponent's coefficients in base 2, so the exponent
 // p log2 e = a dx^2 + b dx dy + c dy^2 = (a dx + b dy) dx + (c dy) dy takes
-// five operations and feeds the hardware 2^x directly (for pmin <= p <= 0,
-// |p log2 e| < 12: the instruction's error stays below 6e-7 relative).
-// pmin2 = pmin log2 e is a per-record lower bound below which o e^p cannot
-// reach alpha_min (ln(alpha_min / o) minus a slack): such pairs skip the
-// exponential; the alpha test itself still decides every pair.
+// five operations and feeds the hardware 2^x directly (for
+// ln(alpha_min / o) <= p <= 0, |p log2 e| < 12: the instruction's error stays
+// below 6e-7 relative).  Callers take a pair only where `in` holds and
+// alpha >= alpha_min.  Below the record's pmin (ln(alpha_min / o) minus a
+// 5e-6 slack) o e^p stays under alpha_min by more than the rounding of the
+// float32 steps, so the alpha test alone rejects those pairs.  With
+// FINITE_G a positive exponent enters 2^x as 0, so that G (which the reverse
+// pass multiplies by zero on skipped pairs) stays finite; without it G and
+// raw may be infinite on skipped pairs, alpha is still at most alpha_max.
+template <bool FINITE_G>
 __device__ __forceinline__ PairAlpha pair_alpha(float pxc, float pyc, const float4 &r0, const float4 &r1,
-                                                float pmin2, float alpha_max) {
+                                                float alpha_max) {
   PairAlpha a;
   a.dx = (pxc - r0.x) - r0.z;
   a.dy = (pyc - r0.y) - r0.w;
   a.t = __fmaf_rn(r1.x, a.dx, r1.y * a.dy);
   a.cdy = r1.z * a.dy;
   const float p2 = __fmaf_rn(a.t, a.dx, a.cdy * a.dy);
-  const float e = __builtin_amdgcn_exp2f(p2);
-  a.G = (p2 > 0.0f || p2 < pmin2) ? -1.0f : e;  // G < 0 marks a skipped pair
+  a.G = __builtin_amdgcn_exp2f(FINITE_G ? fminf(p2, 0.0f) : p2);
+  a.in = !(p2 > 0.0f);
   a.raw = r1.w * a.G;
   // min(raw, alpha_max) as a signed integer minimum of the bit patterns:
   // alpha_max > 0, and raw is either >= 0 (where integer and float order

@@ -186,6 +186,7 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
     res.nb = nb;
     res.cnt = cnt;
     const uint8_t *mine = s_list[wave][row];
+    const bool stopped_before = stopped;
     // each 16-lane row walks its own sub-block's list; a row whose list is
     // shorter idles (valid = false) while the others finish
     for (int k = 0; k < kmax && !done; k++) {
@@ -195,8 +196,8 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
       // pair marked invalid
       const int j = min((int)mine[k], nb - 1);
       const LdsRec R = rec_at(s_rec, j);
-      const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, amax);
-      const bool hit = valid && a.alpha >= o.alpha_min;
+      const PairAlpha a = pair_alpha<false>(pxc, pyc, R.r0, R.r1, amax);
+      const bool hit = valid && a.in && a.alpha >= o.alpha_min;
       const float Tn = T * (1.0f - a.alpha);
       const bool stop = hit && Tn < o.T_min;
       const bool take = hit && !stop;
@@ -211,10 +212,11 @@ __device__ __forceinline__ void tile_forward(const KWs &ws, const KOpts &o, cons
       }
       if (HIST && valid && !stop) hist[(b + j) * 256 + threadIdx.x] = take ? T : 0.0f;
       T = take ? Tn : T;
-      last = stop ? (int)(b + j - c.start) : last;
+      last = stop ? j : last;  // the batch's offset is added below
       stopped = stopped || stop;
       done = stop;
     }
+    if (stopped && !stopped_before) last += (int)(b - c.start);
   }
   if (!stopped) last = c.inside ? (int)(c.end - c.start) : 0;
 }
@@ -323,8 +325,8 @@ __device__ __forceinline__ void tile_backward(const KWs &ws, const KOpts &o, con
       const int jj = min((int)mine[k], nb - 1);  // as in the forward pass
       const int64_t j = lo + jj;
       const LdsRec R = rec_at(s_rec, jj);
-      const PairAlpha a = pair_alpha(pxc, pyc, R.r0, R.r1, R.r2.w, amax);
-      const bool contrib = valid && jj < jj_last && a.alpha >= o.alpha_min;
+      const PairAlpha a = pair_alpha<true>(pxc, pyc, R.r0, R.r1, amax);
+      const bool contrib = valid && a.in && jj < jj_last && a.alpha >= o.alpha_min;
       if (__ballot(contrib) == 0ull) continue;
       // Every lane evaluates the terms (all finite: alpha <= 0.99).  The
       // non-contributing lanes take alpha = 0 here: 1 / (1 - 0) is exactly 1,

@@ -46,8 +46,10 @@ using gsr::LdsRec;
 
 static double U(double a, double b) { return std::uniform_real_distribution<double>(a, b)(g_rng); }
 
-// the per-pair exponent test of the rasterization kernels: pixel (pxc, pyc)
-// can blend the record only if pmin2 <= p2 <= 0
+// a pixel (pxc, pyc) can blend the record only if pmin2 <= p2 <= 0: the
+// kernels skip p2 > 0, and below the record's pmin2 their alpha test cannot
+// pass (o 2^p2 < alpha_min there with margin), so this set holds every pixel
+// the kernels can blend
 static bool pixel_can_blend(const LdsRec &R, float pxc, float pyc) {
   const float dx = (pxc - R.r0.x) - R.r0.z, dy = (pyc - R.r0.y) - R.r0.w;
   const float t = std::fmaf(R.r1.x, dx, R.r1.y * dy);
