@@ -66,14 +66,14 @@ struct StripShape {
 };
 static const StripShape kShapes[3] = {{16, 4, 4, 4, 4}, {32, 2, 8, 2, 4}, {8, 8, 4, 4, 2}};
 
-// one strip: the cull's verdict for each of its four sub-blocks (as the
+// one strip: the cull's outcome for each of its four sub-blocks (as the
 // kernels' sub-list pass takes it), brute force beside it
-struct Verdict {
+struct Outcome {
   bool kept[4], truth[4];
 };
 
-static Verdict judge(const LdsRec &R, const StripShape &sh, float wx0, float wy0) {
-  Verdict v;
+static Outcome classify(const LdsRec &R, const StripShape &sh, float wx0, float wy0) {
+  Outcome v;
   const float wx1 = wx0 + (float)(sh.tw - 1), wy1 = wy0 + (float)(sh.rows - 1);
   const bool strip = gsr::reaches_strip(R, wx0, wx1, wy0, wy1);
   const gsr::ReachShape S = gsr::reach_shape(R);
@@ -128,7 +128,7 @@ int main(int argc, char **argv) {
     const double mx = ox + U(-40.0, 72.0), my = oy + U(-40.0, 48.0);
     const LdsRec R = make_record(s1, s2, th, opac, mx, my, alpha_min);
     thin += gsr::reach_shape(R).thin;
-    const Verdict v = judge(R, kShapes[it % 3], (float)ox + 0.5f, (float)oy + 0.5f);
+    const Outcome v = classify(R, kShapes[it % 3], (float)ox + 0.5f, (float)oy + 0.5f);
     for (int q = 0; q < 4; q++) {
       tests++;
       truth += v.truth[q];
@@ -147,10 +147,10 @@ int main(int argc, char **argv) {
   long special = 0;
   {
     LdsRec R = make_record(3.0, 2.0, 0.3, alpha_min * 0.5, 100.0, 100.0, alpha_min);
-    const Verdict v = judge(R, kShapes[0], 96.5f, 98.5f);
+    const Outcome v = classify(R, kShapes[0], 96.5f, 98.5f);
     for (int q = 0; q < 4; q++) special += v.kept[q];
     R = make_record(0.2, 0.2, 0.0, 0.9, 101.7, 100.2, alpha_min);
-    const Verdict w = judge(R, kShapes[0], 96.5f, 98.5f);
+    const Outcome w = classify(R, kShapes[0], 96.5f, 98.5f);
     special += !w.kept[1] || !w.truth[1];
     R.r1.y = 2.0f * std::sqrt(R.r1.x * R.r1.z) * 1.0001f;  // 4ac - b^2 < 0
     special += !gsr::reach_shape(R).thin;
