@@ -1,9 +1,9 @@
 // Device-side math of the rasterizer: per-Gaussian geometry, projection of
 // one Gaussian into one view, the SH colour, the per-pair compositing step
 // and wavefront reductions.  Everything per Gaussian-view runs in float64
-// (MI355X executes FP64 vector math at half the FP32 rate, and the projected
-// mean must be exact to ~1e-6 px at city-scale coordinates); everything per
-// (pixel, Gaussian) pair runs in float32.
+// (MI355X issues a wave64 FP64 FMA at the rate of an unpacked FP32 one, and
+// the projected mean must be exact to ~1e-6 px at city-scale coordinates);
+// everything per (pixel, Gaussian) pair runs in float32.
 #pragma once
 
 #include <hip/hip_runtime.h>
