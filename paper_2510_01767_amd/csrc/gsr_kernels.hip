@@ -406,7 +406,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_chunks(KWs ws, int64_t lo
                                                                int view_lo, int view_hi, int nchunks) {
   constexpr int kWaves = kScanThreads / 64;
   __shared__ uint64_t s_wave[kWaves];
-  __shared__ uint64_t s_w[kWaves];
   __shared__ uint64_t s_vstart[GSR_MAX_VIEWS];
   uint64_t *sums = reinterpret_cast<uint64_t *>(ws.tile_order);
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
@@ -431,16 +430,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_chunks(KWs ws, int64_t lo
   }
   __syncthreads();
   // where each view's first tile starts: its chunk's prefix plus the counts
-  // in front of it within the chunk
+  // in front of it within the chunk (one wavefront per view, all at once)
   const int nv = view_hi - view_lo;
-  for (int v = 0; v < nv; v++) {
+  for (int v = wave; v < nv; v += kWaves) {
     const int64_t tb = ws.views[view_lo + v].tile_base;
     const int64_t c = (tb - lo) / kScanChunk;
     const int64_t c0 = lo + c * kScanChunk;
     uint64_t part = 0;
-    for (int64_t t = c0 + tid; t < tb; t += kScanThreads) part += tile_total(ws, t, hi);
-    part = block_sum_u64(part, s_w);
-    if (tid == 0) s_vstart[v] = sums[c] + part;
+    for (int64_t t = c0 + lane; t < tb; t += 64) part += tile_total(ws, t, hi);
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) part += __shfl_xor(part, m);
+    if (lane == 0) s_vstart[v] = sums[c] + part;
   }
   __syncthreads();
   const uint64_t cap = (uint64_t)ws.capacity;
